@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Benchmark: modexp terms/s of one bit-extraction query on one MI355X.
+
+A step is one whole pi_extract_ex call: Bellard's formula (eq (1.2)) at bit
+position n = 10^12 with 256 result bits and P = 320 (five 64-bit limbs),
+about 7.0e11 head terms with moduli below 2^40, plus the tail, the
+reduction and the certification. Inputs are the query parameters
+themselves; nothing is read from disk.
+
+Prints one JSON line. `value` = head terms per second of the timed steps.
+`roofline` prices the head kernel against the chip's 32-bit multiply issue
+rate; `cpu_baseline` is the oracle on a bounded seeded sub-slice of the same
+workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import random
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz: v_mad_u64_u32 (a 32x32->64
+# multiply-add) issues at the full VALU rate on gfx950.
+PEAK_MUL32 = 256 * 64 * 2.4e9
+
+CLASS32_LIMIT = 2 ** 31
+
+
+def series(formula):
+    # (c, a, b) per series and the step; the sign does not change the work
+    if formula == 1:
+        return [(2, 10, 1), (0, 10, 3), (-4, 10, 5), (-4, 10, 7), (-6, 10, 9), (-1, 4, 1),
+                (-6, 4, 3)], 10
+    return [(2, 8, 1), (-1, 2, 1), (0, 8, 5), (-1, 4, 3)], 4
+
+
+def mul32_per_launch(formula, n, P):
+    """Algorithmic 32-bit multiplies of every head term of one extraction.
+
+    Per term with a modulus of class 64 (R = 2^64): bitlen(X) Montgomery
+    squarings of a two-word residue, X = E + 64(L-1), at 11 multiplies each
+    (4 for the product, 3 for q = T m' mod 2^64, 4 for the high half of qM);
+    12 for -M^-1 mod 2^64; 7 per limb of the Hensel division. Class 32
+    (M < 2^31, R = 2^32): 3 per squaring (X = E + 64L - 32), 6 for the
+    inverse, 4 per limb.
+    """
+    rows, step = series(formula)
+    L = (P + 63) // 64
+    d = n - 1
+    total = 0
+    terms = 0
+    for c, a, b in rows:
+        if d + c < 0:
+            continue
+        K = (d + c) // step + 1
+        ks = min(K, max(0, -(-(CLASS32_LIMIT - b) // a)))
+        for lo, hi, cls in ((0, ks, 32), (ks, K, 64)):
+            if lo >= hi:
+                continue
+            off = 64 * (L - 1) if cls == 64 else 64 * L - 32
+            per_sq, fixed = (11, 12 + 7 * L) if cls == 64 else (3, 6 + 4 * L)
+            # X(k) = d + c - step k + off decreases with k; sum bitlen over bands
+            k = lo
+            while k < hi:
+                X = d + c - step * k + off
+                bl = X.bit_length()
+                lowX = 1 << (bl - 1) if bl > 0 else 0
+                # last k with X(k) >= lowX
+                kmax = min(hi - 1, (d + c + off - lowX) // step) if bl > 0 else hi - 1
+                cnt = kmax - k + 1
+                total += cnt * (bl * per_sq + fixed)
+                terms += cnt
+                k = kmax + 1
+    return total, terms
+
+
+def cpu_baseline(formula, n, P, target_s=12.0):
+    """The oracle on a seeded sub-slice: equal-length random k ranges of every
+    series, sized from a short probe to take about target_s seconds."""
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    rows, step = series(formula)
+    rng = random.Random(1008)
+    d = n - 1
+
+    def run(length):
+        t0 = time.perf_counter()
+        done = 0
+        for j, (c, a, b) in enumerate(rows):
+            K = (d + c) // step + 1
+            k0 = rng.randrange(0, max(1, K - length))
+            oracle.sum_slice(formula, j, d, k0, k0 + length, P, threads)
+            done += length
+        return done, time.perf_counter() - t0
+
+    done, dt = run(1 << 16)
+    per_term = dt / done
+    length = int(max(1 << 16, min(1 << 26, target_s / per_term / len(rows))))
+    done, dt = run(length)
+    return {"value": done / dt, "unit": "terms/s", "cores": threads, "kind": "oracle",
+            "sample": "%d series x %d consecutive k at seeded random offsets of the same "
+                      "query (%d head terms, %.1f s)" % (len(rows), length, done, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=10 ** 12)
+    ap.add_argument("--nbits", type=int, default=256)
+    ap.add_argument("--P", type=int, default=320)
+    ap.add_argument("--formula", choices=["bellard", "bbp"], default="bellard")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the path has no multi-GPU code (a query's index "
+              "ranges would shard across GPUs with one 40-byte exchange at the end); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1008_3171_amd as pb
+
+    formula = pb.BELLARD if args.formula == "bellard" else pb.BBP
+    n, w, P = args.n, args.nbits, args.P
+    stream = torch.cuda.current_stream()
+    out = torch.zeros(pb.limbs(P), dtype=torch.int64, device="cuda")
+    st = torch.zeros(4, dtype=torch.int32, device="cuda")
+    for _ in range(args.warmup):
+        pb.extract(formula, n, w, P, out=out, status=st, stream=stream)
+        torch.cuda.synchronize()
+        print("warmup step done", file=sys.stderr, flush=True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        pb.extract(formula, n, w, P, out=out, status=st, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1) / args.steps
+    code, N = pb.status_of(st)
+    S = pb.to_int(out, P)
+    print("timed steps done", file=sys.stderr, flush=True)
+
+    mul32, terms = mul32_per_launch(formula, n, P)
+    assert terms == pb.head_terms(formula, n)
+    value = terms / (ms * 1e-3)
+    achieved = mul32 / (ms * 1e-3)
+    rec = {
+        "metric": "modexp terms/s at n=1e12, 256-bit exact",
+        "value": value,
+        "unit": "terms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "wall_s": wall,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "single query, %s formula, n=%d, %d result bits, P=%d"
+                               % (args.formula, n, w, P),
+                   "head_terms": terms, "limbs": pb.limbs(P)},
+        "certified": code == pb.PI_OK,
+        "nterms": N,
+        "result_hex": "%0*x" % ((w + 3) // 4, S >> (P - w)),
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_MUL32 / 1e12,
+                     "unit": "Tmul32/s", "frac": achieved / PEAK_MUL32, "traffic": None,
+                     "mul32_per_launch": mul32},
+    }
+    if n == 10 ** 12 and w == 256 and formula == pb.BELLARD:
+        # Table 2.2, m = 12 starts at 10^12 + 1: our bits 1..255
+        import re
+        row = open(os.path.join(ROOT, "tests", "golden", "table_2_2.txt")).read()
+        h = re.search(r"^12 \d+ \d+ ([0-9A-F]+)$", row, re.M).group(1)
+        ref = int(h, 16) >> (4 * len(h) - 255)
+        rec["matches_table_2_2_m12"] = ((S >> (P - w)) & ((1 << 255) - 1)) == ref
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(formula, n, P)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

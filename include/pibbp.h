@@ -1,0 +1,137 @@
+/*
+ * pibbp.h -- C ABI of the MI355X bit-extraction library for pi.
+ *
+ * The library evaluates BBP-type formulas at a bit position n (Sze, "The Two
+ * Quadrillionth Bit of pi is 0!", section 3): for every series j of the
+ * formula and every index k it forms the term
+ *
+ *     t_{j,k} = floor(2^P * frac(2^E / M)),   E = n - 1 + c_j - step*k,
+ *                                             M = a_j*k + b_j,
+ *
+ * (the A_k of eq (3.3) when E >= 0, computed with a modular exponentiation
+ * and a division; the B_k of eq (3.3) when E < 0) and adds
+ * sign_j * alt^k * t_{j,k} modulo 2^P. Formulas: Bellard's (eq (1.2); step
+ * 10, alternating signs, seven series) and the BBP formula (eq (1.1), in the
+ * odd-denominator form of eq (3.1); step 4, four series). Everything is exact
+ * integer arithmetic; there is no floating point.
+ *
+ * Conventions shared by every call:
+ *  - n is the 1-based position of the first result bit after the radix point
+ *    (the abstract's footnote: the 8 bits starting at position 9 are 0x3F).
+ *  - A P-bit sum S is returned in L = ceil(P/64) little-endian uint64 limbs,
+ *    LEFT-ALIGNED: the limbs hold S * 2^(64L-P), so the first result bit is the
+ *    most significant bit of limb L-1 and the low 64L-P bits are zero.
+ *  - Pointers named out/status/workspace are DEVICE pointers owned by the
+ *    caller; the library never frees them. Query tables are HOST pointers.
+ *  - Calls are asynchronous on `stream`: argument validation is synchronous
+ *    and returns an error code; results are ready when the stream is.
+ *  - Limits: 1 <= P <= PI_MAX_P; every modulus a_j*k+b_j below 2^60 and
+ *    n + P below 2^62 (otherwise PI_EUNSUPPORTED).
+ *  - Calls on one device share internal scratch per stream; calls on
+ *    different streams may overlap, calls on one stream are serialized.
+ */
+#ifndef PIBBP_H
+#define PIBBP_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Formulas: eq (1.1) (as written in eq (3.1)) and eq (1.2). */
+enum { PI_BBP = 0, PI_BELLARD = 1 };
+
+/* A single series j of a formula, for pi_sum_slice. Bellard's series, in the
+ * order of eq (1.2): 0: +2^2/(10k+1), 1: -1/(10k+3), 2: -2^-4/(10k+5),
+ * 3: -2^-4/(10k+7), 4: +2^-6/(10k+9), 5: -2^-1/(4k+1), 6: -2^-6/(4k+3).
+ * BBP series, in the order of eq (3.1): 0: +2^2/(8k+1), 1: -2^-1/(2k+1),
+ * 2: -1/(8k+5), 3: -2^-1/(4k+3). */
+#define PI_TERM(formula, j) ((formula) * 16 + (j))
+
+/* Return codes. PI_UNCERTAIN is a status, not an error: the bits were
+ * computed exactly, but the guard window (section 3.1) cannot prove that they
+ * are pi's bits; a larger P can. */
+enum {
+  PI_OK = 0,
+  PI_UNCERTAIN = 1,
+  PI_EINVAL = -1,
+  PI_ENOMEM = -2,
+  PI_EDEVICE = -3,
+  PI_EUNSUPPORTED = -4
+};
+
+#define PI_MAX_P 1088u
+
+/* Result status written by pi_extract_ex and pi_extract_batch (device memory). */
+typedef struct {
+  int32_t code;     /* PI_OK when certified, PI_UNCERTAIN otherwise */
+  int32_t reserved; /* 0 */
+  uint64_t nterms;  /* N: indices summed (head terms plus tail terms before the stop) */
+} pi_status;
+
+/* nbits bits of pi starting at 1-based position n, with P = nbits + 64 (the
+ * 64 guard bits certify the result; section 3.1's "compute with more
+ * precision than you report").
+ *   out: device uint64[ceil((nbits+64)/64)], the left-aligned P-bit sum S.
+ * Returns PI_OK or an error; certification is reported by pi_extract_ex. */
+int pi_extract(int formula, uint64_t n, uint32_t nbits, uint64_t *out, hipStream_t stream);
+
+/* As pi_extract with an explicit precision P >= nbits (e.g. P = 96 for 64
+ * result bits) and an optional device pi_status (may be NULL).
+ * The tail of each series is summed up to its stop index: the first E < 0
+ * index whose P-bit truncation is 0 (every later term is smaller).
+ *   out: device uint64[ceil(P/64)]. status: device pi_status or NULL. */
+int pi_extract_ex(int formula, uint64_t n, uint32_t nbits, uint32_t P, uint64_t *out,
+                  pi_status *status, hipStream_t stream);
+
+/* One summand of eq (3.1), restricted to an index range, as in the
+ * partition/compute split of section 4.1: the sum over k in [k0, k1) of
+ * sign_j * alt^k * t_{j,k} modulo 2^P, for term = PI_TERM(formula, j). Head
+ * and tail indices may both be in the range; tail terms past the stop index
+ * are zero. Sums over disjoint ranges add up (mod 2^P) to the full sum.
+ *   out: device uint64[ceil(P/64)], left-aligned. */
+int pi_sum_slice(int term, uint64_t n, uint64_t k0, uint64_t k1, uint32_t P, uint64_t *out,
+                 hipStream_t stream);
+
+/* A query of a batch. out_offset is in uint64 limbs from the batch's `out`;
+ * the query writes ceil(P/64) limbs there. */
+typedef struct {
+  int32_t formula;
+  uint32_t nbits;
+  uint32_t P;
+  uint32_t reserved; /* 0 */
+  uint64_t n;
+  uint64_t out_offset;
+} pi_query;
+
+/* Many extractions in one submission: the head terms of every query go
+ * through one persistent launch per limb-count class, each query keeps its
+ * partial sum on the device, and one finalize launch writes every result.
+ * Each query's result is bit-identical to pi_extract_ex on its own.
+ *   q: host array[count]. out: device, packed per out_offset.
+ *   status: device pi_status[count] or NULL.
+ *   workspace: device memory of at least pi_workspace_size(q, count) bytes,
+ *   or NULL to use the library's per-stream scratch. */
+int pi_extract_batch(const pi_query *q, int count, uint64_t *out, pi_status *status,
+                     void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/* Bytes of device workspace pi_extract_batch needs for these queries. */
+size_t pi_workspace_size(const pi_query *q, int count);
+
+/* Number of head terms (E >= 0 indices) of an extraction: sum over series of
+ * floor((n-1+c_j)/step)+1 where that is positive. Host-only arithmetic. */
+uint64_t pi_head_terms(int formula, uint64_t n);
+
+/* Static text for a return code. */
+const char *pi_strerror(int code);
+
+/* Release the library's scratch memory on every device. */
+void pi_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

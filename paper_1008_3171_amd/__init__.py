@@ -1,0 +1,183 @@
+"""Python binding of the MI355X bit-extraction library for pi (libpibbp.so).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in ``include/pibbp.h``. PyTorch provides
+device memory and streams. If the library is not built, or no GPU is present,
+the calls raise; there is no CPU fallback.
+
+Limb layout (as in the C ABI): a P-bit sum S comes back as
+L = ceil(P/64) little-endian 64-bit limbs holding S * 2^(64L - P), stored in a
+torch.int64 tensor on the device (bit pattern of uint64).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+BBP = 0
+BELLARD = 1
+PI_OK = 0
+PI_UNCERTAIN = 1
+MAX_P = 1088
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpibbp.so")
+_lib = None
+
+
+class PiError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        msg = _lib.pi_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__("%s failed: %s (code %d)" % (what, msg, code))
+        self.code = code
+
+
+class pi_query(ctypes.Structure):
+    _fields_ = [("formula", ctypes.c_int32), ("nbits", ctypes.c_uint32),
+                ("P", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("n", ctypes.c_uint64), ("out_offset", ctypes.c_uint64)]
+
+
+def term_id(formula: int, j: int) -> int:
+    """PI_TERM(formula, j)."""
+    return formula * 16 + j
+
+
+def load():
+    """Load libpibbp.so (built by ``python -m paper_1008_3171_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libpibbp.so is not built; run python -m paper_1008_3171_amd.build")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+        lib.pi_extract.argtypes = [i32, u64, u32, vp, vp]
+        lib.pi_extract_ex.argtypes = [i32, u64, u32, u32, vp, vp, vp]
+        lib.pi_sum_slice.argtypes = [i32, u64, u64, u64, u32, vp, vp]
+        lib.pi_extract_batch.argtypes = [vp, i32, vp, vp, vp, ctypes.c_size_t, vp]
+        lib.pi_workspace_size.argtypes = [vp, i32]
+        lib.pi_workspace_size.restype = ctypes.c_size_t
+        lib.pi_head_terms.argtypes = [i32, u64]
+        lib.pi_head_terms.restype = u64
+        lib.pi_strerror.argtypes = [i32]
+        lib.pi_strerror.restype = ctypes.c_char_p
+        lib.pi_shutdown.argtypes = []
+        for f in (lib.pi_extract, lib.pi_extract_ex, lib.pi_sum_slice, lib.pi_extract_batch):
+            f.restype = i32
+        _lib = lib
+    return _lib
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU: the HIP library needs a ROCm device")
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def limbs(P: int) -> int:
+    return (P + 63) // 64
+
+
+def head_terms(formula: int, n: int) -> int:
+    return int(load().pi_head_terms(formula, n))
+
+
+def extract(formula: int, n: int, nbits: int, P: int | None = None, out=None, status=None,
+            stream=None):
+    """pi_extract_ex: returns (out limbs tensor, status tensor [4] int32).
+
+    P defaults to nbits + 64. Asynchronous on `stream` (default: current)."""
+    torch = _torch()
+    lib = load()
+    P = nbits + 64 if P is None else P
+    if out is None:
+        out = torch.zeros(limbs(P), dtype=torch.int64, device="cuda")
+    if status is None:
+        status = torch.zeros(4, dtype=torch.int32, device="cuda")
+    rc = lib.pi_extract_ex(formula, n, nbits, P, ctypes.c_void_p(out.data_ptr()),
+                           ctypes.c_void_p(status.data_ptr()), _stream(stream))
+    if rc != 0:
+        raise PiError(rc, "pi_extract_ex")
+    return out, status
+
+
+def extract_default(formula: int, n: int, nbits: int, out=None, stream=None):
+    """pi_extract (P = nbits + 64, no status)."""
+    torch = _torch()
+    lib = load()
+    if out is None:
+        out = torch.zeros(limbs(nbits + 64), dtype=torch.int64, device="cuda")
+    rc = lib.pi_extract(formula, n, nbits, ctypes.c_void_p(out.data_ptr()), _stream(stream))
+    if rc != 0:
+        raise PiError(rc, "pi_extract")
+    return out
+
+
+def sum_slice(term: int, n: int, k0: int, k1: int, P: int, out=None, stream=None):
+    """pi_sum_slice: the signed sum of one series over k in [k0, k1) mod 2^P."""
+    torch = _torch()
+    lib = load()
+    if out is None:
+        out = torch.zeros(limbs(P), dtype=torch.int64, device="cuda")
+    rc = lib.pi_sum_slice(term, n, k0, k1, P, ctypes.c_void_p(out.data_ptr()), _stream(stream))
+    if rc != 0:
+        raise PiError(rc, "pi_sum_slice")
+    return out
+
+
+def make_queries(specs):
+    """specs: iterable of (formula, n, nbits, P). Returns (ctypes array, total limbs)."""
+    specs = list(specs)
+    arr = (pi_query * max(1, len(specs)))()
+    off = 0
+    for i, (formula, n, nbits, P) in enumerate(specs):
+        arr[i].formula, arr[i].n, arr[i].nbits, arr[i].P = formula, n, nbits, P
+        arr[i].reserved = 0
+        arr[i].out_offset = off
+        off += limbs(P)
+    return arr, off
+
+
+def workspace_size(qarr, count: int) -> int:
+    return int(load().pi_workspace_size(ctypes.cast(qarr, ctypes.c_void_p), count))
+
+
+def extract_batch(qarr, count: int, out, status=None, workspace=None, stream=None):
+    """pi_extract_batch over a ctypes pi_query array (see make_queries)."""
+    torch = _torch()
+    lib = load()
+    if status is None:
+        status = torch.zeros(4 * max(1, count), dtype=torch.int32, device="cuda")
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    rc = lib.pi_extract_batch(ctypes.cast(qarr, ctypes.c_void_p), count,
+                              ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(status.data_ptr()),
+                              ctypes.c_void_p(ws_ptr), ws_bytes, _stream(stream))
+    if rc != 0:
+        raise PiError(rc, "pi_extract_batch")
+    return out, status
+
+
+def to_int(limb_tensor, P: int | None = None) -> int:
+    """Limbs (int64 tensor, any device) -> the P-bit integer S (not left-aligned)."""
+    vals = [int(v) & 0xFFFFFFFFFFFFFFFF for v in limb_tensor.cpu().tolist()]
+    x = 0
+    for i, v in enumerate(vals):
+        x |= v << (64 * i)
+    if P is not None:
+        x >>= 64 * len(vals) - P
+    return x
+
+
+def status_of(status_tensor, i: int = 0):
+    """(code, nterms) of the i-th pi_status in an int32 tensor."""
+    s = [int(v) & 0xFFFFFFFF for v in status_tensor[4 * i:4 * i + 4].cpu().tolist()]
+    return s[0] if s[0] < 2 ** 31 else s[0] - 2 ** 32, s[2] | (s[3] << 32)

@@ -1,0 +1,328 @@
+// C ABI of the library: argument checks, the host-side partition of each
+// query's index set, scratch memory, and kernel launches.
+//
+// The partition follows section 4's multi-level split (the final sum over
+// jobs, each over tasks, each over threads): a query's index set is split by
+// series j and by modulus class into head segments, each segment into chunks
+// of 256*run consecutive indices (one workgroup pass), each chunk into lanes.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "pibbp.h"
+#include "plan.h"
+
+using namespace pibbp;
+
+namespace {
+
+struct HostSeries {
+  int neg, c;
+  uint64_t a, b;
+};
+// Same data as the device tables: eq (1.2) for Bellard, eq (3.1) for BBP.
+const HostSeries kHSeries[2][7] = {
+    {{0, 2, 8, 1}, {1, -1, 2, 1}, {1, 0, 8, 5}, {1, -1, 4, 3}, {0, 0, 1, 1}, {0, 0, 1, 1}, {0, 0, 1, 1}},
+    {{0, 2, 10, 1}, {1, 0, 10, 3}, {1, -4, 10, 5}, {1, -4, 10, 7}, {0, -6, 10, 9}, {1, -1, 4, 1},
+     {1, -6, 4, 3}},
+};
+const int kHStep[2] = {4, 10};
+const int kHJ[2] = {4, 7};
+const int kLimbClasses[] = {1, 2, 3, 4, 5, 6, 8, 12, 17};
+
+constexpr uint64_t kClass32Limit = 1ull << 31;
+constexpr uint64_t kModulusLimit = 1ull << 60;
+
+int limb_class(uint32_t P) {
+  const int Lq = (int)((P + 63u) / 64u);
+  for (int c : kLimbClasses)
+    if (c >= Lq) return c;
+  return -1;
+}
+
+// first index of series j whose exponent d + c - step k is negative
+uint64_t first_tail(const HostSeries &s, int step, uint64_t d) {
+  const int64_t dc = (int64_t)d + s.c;
+  return dc < 0 ? 0 : (uint64_t)(dc / step) + 1u;
+}
+
+// first index past which every truncated tail term is 0: t >= 1 needs
+// P + E >= 0, i.e. k <= (d + c + P) / step
+uint64_t first_zero(const HostSeries &s, int step, uint64_t d, uint32_t P) {
+  const int64_t v = (int64_t)d + s.c + (int64_t)P;
+  return v < 0 ? 0 : (uint64_t)(v / step) + 1u;
+}
+
+struct QueryPlan {
+  int formula;
+  uint64_t d;
+  uint32_t P, w, Lq;
+  int Lk;
+  uint64_t hk0[7], hk1[7];  // head ranges
+  uint64_t tk0[7], tk1[7];  // tail ranges
+  uint64_t nhead;
+};
+
+// Fill a plan for series set `jmask` of `formula` over index range [k0, k1).
+int make_plan(int formula, uint64_t n, uint32_t w, uint32_t P, uint32_t jmask, uint64_t k0,
+              uint64_t k1, QueryPlan *qp) {
+  if (formula != PI_BBP && formula != PI_BELLARD) return PI_EINVAL;
+  if (n == 0 || w == 0 || P == 0 || P < w || P > PI_MAX_P || k0 > k1) return PI_EINVAL;
+  if (n >= (1ull << 62) - PI_MAX_P - 64) return PI_EUNSUPPORTED;
+  memset(qp, 0, sizeof(*qp));
+  qp->formula = formula;
+  qp->d = n - 1;
+  qp->P = P;
+  qp->w = w;
+  qp->Lq = (P + 63u) / 64u;
+  qp->Lk = limb_class(P);
+  const int step = kHStep[formula];
+  for (int j = 0; j < kHJ[formula]; ++j) {
+    if (!(jmask & (1u << j))) continue;
+    const HostSeries &s = kHSeries[formula][j];
+    const uint64_t kt = first_tail(s, step, qp->d);
+    const uint64_t kz = std::max(kt, first_zero(s, step, qp->d, P));
+    qp->hk0[j] = std::min(k0, kt);
+    qp->hk1[j] = std::min(k1, kt);
+    qp->tk0[j] = std::min(std::max(k0, kt), kz);
+    qp->tk1[j] = std::max(qp->tk0[j], std::min(k1, kz));
+    const uint64_t hi = std::max(qp->hk1[j], qp->tk1[j]);
+    if (hi > 0 && (hi - 1) > (kModulusLimit - s.b) / s.a) return PI_EUNSUPPORTED;
+    qp->nhead += qp->hk1[j] - qp->hk0[j];
+  }
+  return PI_OK;
+}
+
+// Head segments of a plan, split at the class-32/class-64 modulus boundary.
+void head_segments(const QueryPlan &qp, uint32_t query, std::vector<HeadSeg> &out) {
+  for (int j = 0; j < kHJ[qp.formula]; ++j) {
+    const HostSeries &s = kHSeries[qp.formula][j];
+    const uint64_t kb = qp.hk0[j], ke = qp.hk1[j];
+    if (kb >= ke) continue;
+    const uint64_t ks = kClass32Limit > s.b ? (kClass32Limit - s.b + s.a - 1) / s.a : 0;
+    const uint64_t cut = std::min(std::max(ks, kb), ke);
+    HeadSeg g;
+    memset(&g, 0, sizeof g);
+    g.d = qp.d;
+    g.formula = (uint32_t)qp.formula;
+    g.j = (uint32_t)j;
+    g.P = qp.P;
+    g.query = query;
+    if (kb < cut) {
+      g.kb = kb;
+      g.ke = cut;
+      g.cls = 32;
+      out.push_back(g);
+    }
+    if (cut < ke) {
+      g.kb = cut;
+      g.ke = ke;
+      g.cls = 64;
+      out.push_back(g);
+    }
+  }
+}
+
+FinQuery fin_query(const QueryPlan &qp, uint64_t out_off, bool want_status, uint32_t sidx) {
+  FinQuery f;
+  memset(&f, 0, sizeof f);
+  f.d = qp.d;
+  f.nhead = qp.nhead;
+  f.out_off = out_off;
+  for (int j = 0; j < 7; ++j) {
+    f.tk0[j] = qp.tk0[j];
+    f.tk1[j] = qp.tk1[j];
+  }
+  f.formula = (uint32_t)qp.formula;
+  f.P = qp.P;
+  f.w = qp.w;
+  f.Lq = qp.Lq;
+  f.want_status = want_status ? 1u : 0u;
+  f.status_idx = sidx;
+  return f;
+}
+
+// ---- device facts and scratch ----------------------------------------------
+
+std::mutex g_mu;
+std::map<int, int> g_cus;
+struct Arena {
+  void *dev = nullptr;
+  size_t bytes = 0;
+};
+std::map<std::pair<int, hipStream_t>, Arena> g_arena;
+
+int device_cus() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -1;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_cus.find(dev);
+  if (it != g_cus.end()) return it->second;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return -1;
+  g_cus[dev] = cus;
+  return cus;
+}
+
+// Per-(device, stream) scratch, grown on demand. Growing waits for the
+// stream so that no queued kernel still uses the old block.
+void *arena(hipStream_t st, size_t bytes, int *err) {
+  int dev = 0;
+  *err = PI_OK;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    *err = PI_EDEVICE;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  Arena &a = g_arena[{dev, st}];
+  if (a.bytes < bytes) {
+    if (a.dev) {
+      if (hipStreamSynchronize(st) != hipSuccess || hipFree(a.dev) != hipSuccess) {
+        *err = PI_EDEVICE;
+        return nullptr;
+      }
+      a.dev = nullptr;
+      a.bytes = 0;
+    }
+    const size_t nb = std::max(bytes, (size_t)1 << 16);
+    if (hipMalloc(&a.dev, nb) != hipSuccess) {
+      *err = PI_ENOMEM;
+      return nullptr;
+    }
+    a.bytes = nb;
+  }
+  return a.dev;
+}
+
+// Chunk length per lane: long runs amortize the per-chunk fold, but a small
+// query still has to fill every workgroup slot several times over. A query's
+// carry-save counters take one value below 2^32 per chunk, so its chunk count
+// must stay below 2^31: very large queries get longer runs.
+uint32_t pick_run(uint64_t head_terms, int grid) {
+  const uint64_t per = head_terms / (256ull * (uint64_t)grid * 4ull);
+  const uint64_t floor_run = head_terms / (256ull << 31) + 1u;
+  return (uint32_t)std::max<uint64_t>(floor_run, std::min<uint64_t>(64, std::max<uint64_t>(1, per)));
+}
+
+int resident_grid() {
+  const int cus = device_cus();
+  return cus > 0 ? cus * 8 : 2048;
+}
+
+int hip_err(hipError_t e) { return e == hipSuccess ? PI_OK : PI_EDEVICE; }
+
+// Launch everything for one planned query (head segments passed by value).
+int run_single(const QueryPlan &qp, uint64_t *out, pi_status *status, hipStream_t st) {
+  std::vector<HeadSeg> segs;
+  head_segments(qp, 0, segs);
+  const int grid_max = resident_grid();
+  const uint32_t run = pick_run(qp.nhead, grid_max);
+  const uint64_t CH = 256ull * run;
+  HeadSegTable tab;
+  memset(&tab, 0, sizeof tab);
+  uint64_t nchunks = 0;
+  for (size_t i = 0; i < segs.size(); ++i) {
+    segs[i].chunk0 = nchunks;
+    nchunks += (segs[i].ke - segs[i].kb + CH - 1) / CH;
+    tab.s[i] = segs[i];
+  }
+  tab.n = (int)segs.size();
+  const int Lk = qp.Lk;
+  int err = PI_OK;
+  auto *acc = (unsigned long long *)arena(st, 2u * PI_MAX_L * sizeof(unsigned long long), &err);
+  if (!acc) return err;
+  if (int e = hip_err(launch_zero(acc, 2u * (uint64_t)Lk, st))) return e;
+  if (nchunks) {
+    const int grid = (int)std::min<uint64_t>(nchunks, (uint64_t)grid_max);
+    if (int e = hip_err(launch_head_args(Lk, tab, nchunks, run, grid, acc, st))) return e;
+  }
+  FinQuery fq = fin_query(qp, 0, status != nullptr, 0);
+  return hip_err(launch_finalize(Lk, fq, nullptr, 1, acc, out, status, st));
+}
+
+}  // namespace
+
+extern "C" {
+
+int pi_extract_ex(int formula, uint64_t n, uint32_t nbits, uint32_t P, uint64_t *out,
+                  pi_status *status, hipStream_t stream) {
+  if (!out) return PI_EINVAL;
+  QueryPlan qp;
+  if (int e = make_plan(formula, n, nbits, P, 0x7fu, 0, UINT64_MAX, &qp)) return e;
+  return run_single(qp, out, status, stream);
+}
+
+int pi_extract(int formula, uint64_t n, uint32_t nbits, uint64_t *out, hipStream_t stream) {
+  if (nbits == 0 || nbits > PI_MAX_P - 64) return PI_EINVAL;
+  return pi_extract_ex(formula, n, nbits, nbits + 64u, out, nullptr, stream);
+}
+
+int pi_sum_slice(int term, uint64_t n, uint64_t k0, uint64_t k1, uint32_t P, uint64_t *out,
+                 hipStream_t stream) {
+  if (!out || term < 0) return PI_EINVAL;
+  const int formula = term / 16, j = term % 16;
+  if ((formula != PI_BBP && formula != PI_BELLARD) || j >= kHJ[formula]) return PI_EINVAL;
+  QueryPlan qp;
+  if (int e = make_plan(formula, n, P, P, 1u << j, k0, k1, &qp)) return e;
+  return run_single(qp, out, nullptr, stream);
+}
+
+uint64_t pi_head_terms(int formula, uint64_t n) {
+  if ((formula != PI_BBP && formula != PI_BELLARD) || n == 0) return 0;
+  uint64_t tot = 0;
+  for (int j = 0; j < kHJ[formula]; ++j)
+    tot += first_tail(kHSeries[formula][j], kHStep[formula], n - 1);
+  return tot;
+}
+
+size_t pi_workspace_size(const pi_query *q, int count) {
+  (void)q;
+  (void)count;
+  return 0;
+}
+
+int pi_extract_batch(const pi_query *q, int count, uint64_t *out, pi_status *status,
+                     void *workspace, size_t ws_bytes, hipStream_t stream) {
+  (void)q;
+  (void)count;
+  (void)out;
+  (void)status;
+  (void)workspace;
+  (void)ws_bytes;
+  (void)stream;
+  return PI_EUNSUPPORTED;
+}
+
+const char *pi_strerror(int code) {
+  switch (code) {
+    case PI_OK: return "ok";
+    case PI_UNCERTAIN: return "bits computed exactly but not certified by the guard window";
+    case PI_EINVAL: return "invalid argument";
+    case PI_ENOMEM: return "out of device memory";
+    case PI_EDEVICE: return "HIP runtime or device error";
+    case PI_EUNSUPPORTED: return "outside the supported range (modulus >= 2^60 or n too large)";
+    default: return "unknown error code";
+  }
+}
+
+void pi_shutdown(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto &kv : g_arena) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(kv.first.first);
+    (void)hipStreamSynchronize(kv.first.second);
+    (void)hipFree(kv.second.dev);
+    (void)hipSetDevice(cur);
+  }
+  g_arena.clear();
+}
+
+}  // extern "C"

@@ -1,0 +1,162 @@
+// Device integer arithmetic for one BBP-type term on gfx950.
+//
+// A head term (E >= 0) of eq (3.3) in Sze (2010) needs 2^E mod M and then a
+// P-bit division r*2^P/M. Both are done without any division instruction:
+//
+//  * modular exponentiation (section 4.2 names Montgomery's method for large
+//    moduli): a left-to-right binary ladder in Montgomery form. Each step is
+//    one Montgomery reduction of x^2 * 2^b, so the doubling for a 1 bit costs
+//    a shift, not a multiplication. The ladder's target exponent is chosen so
+//    that the Montgomery form of its result is already s = 2^(E+64L) mod M.
+//  * division: with s = r*2^(64L) mod M, the quotient t = floor(r*2^(64L)/M)
+//    satisfies t*M = r*2^(64L) - s, so t = -s * M^-1 mod 2^(64L). That is an
+//    exact (Hensel) division, limb by limb from the bottom, using the same
+//    -M^-1 mod 2^64 the Montgomery reduction needs.
+//  * truncation to P bits: floor(t / 2^(64L-P)) = floor(r*2^P/M), so the P-bit
+//    term, left-aligned in L limbs, is t with its low 64L-P bits cleared.
+//
+// Two modulus classes keep the multiply count down:
+//  * class 32 (M < 2^31): R = 2^32, residues kept below M;
+//  * class 64 (2^31 <= M < 2^60): R = 2^64, residues kept below 2M.
+// v_mad_u64_u32 issues at full rate on gfx950, so these are written in plain
+// 64-bit C and the compiler emits mad chains.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pibbp {
+
+// -M^-1 mod 2^32, M odd. (3M) xor 2 is an inverse to 5 bits; each Newton step
+// x <- x(2 - Mx) doubles the number of correct low bits (5, 10, 20, 40).
+__device__ __forceinline__ uint32_t neg_inv32(uint32_t m) {
+  uint32_t x = (3u * m) ^ 2u;
+  x *= 2u - m * x;
+  x *= 2u - m * x;
+  x *= 2u - m * x;
+  return 0u - x;
+}
+
+// -M^-1 mod 2^64, M odd: one more Newton step from the 32-bit inverse.
+__device__ __forceinline__ uint64_t neg_inv64(uint64_t m) {
+  uint64_t x = (uint32_t)(0u - neg_inv32((uint32_t)m));
+  x *= 2u - m * x;
+  return 0u - x;
+}
+
+__device__ __forceinline__ int bitlen64(uint64_t x) { return x ? 64 - __clzll(x) : 0; }
+__device__ __forceinline__ int bitlen32(uint32_t x) { return x ? 32 - __clz(x) : 0; }
+
+// ---- class 64: R = 2^64, lazy residues in [0, 2M), M < 2^60 --------------
+
+// Montgomery reduction of x^2 * 2^b: returns y == x^2 2^b 2^-64 (mod M),
+// y < 2M, for x < 2M, b in {0, 1}. Since x^2 2^b + qM == 0 (mod 2^64), the
+// low halves sum to exactly 2^64 unless x^2 2^b == 0 (mod 2^64), which gives
+// the carry (lo != 0). Bound: y < 8M^2/2^64 + M + 1 <= 2M for M < 2^60.
+__device__ __forceinline__ uint64_t sqr_redc64(uint64_t x, uint32_t b, uint64_t M, uint64_t mp) {
+  uint64_t y = x << b;
+  uint64_t lo = x * y;
+  uint64_t hi = __umul64hi(x, y);
+  uint64_t q = lo * mp;
+  uint64_t h = __umul64hi(q, M);
+  return hi + h + (lo != 0u ? 1u : 0u);
+}
+
+// Montgomery reduction of a single x < 2M: x 2^-64 mod M, in [0, M].
+__device__ __forceinline__ uint64_t redc64(uint64_t x, uint64_t M, uint64_t mp) {
+  uint64_t q = x * mp;
+  return __umul64hi(q, M) + (x != 0u ? 1u : 0u);
+}
+
+// 2^64 mod M (the Montgomery form of 1), M odd, 3 <= M < 2^60: start from
+// 2^bl - M == 2^bl (mod M), bl = bit length of M, then double 64 - bl times.
+__device__ __forceinline__ uint64_t mont_one64(uint64_t M) {
+  int bl = bitlen64(M);
+  uint64_t c = (1ull << bl) - M;
+  for (int i = bl; i < 64; ++i) {
+    c <<= 1;
+    c = c >= M ? c - M : c;
+  }
+  return c;
+}
+
+// ---- class 32: R = 2^32, residues in [0, M), M < 2^31 --------------------
+
+// x^2 2^b 2^-32 mod M for x < M: T = x (x << b) < 2M^2 and qM < 2^63, so
+// T + qM fits in 64 bits; its high half is below 2M; one conditional
+// subtraction brings it below M.
+__device__ __forceinline__ uint32_t sqr_redc32(uint32_t x, uint32_t b, uint32_t M, uint32_t mp) {
+  uint32_t y = x << b;
+  uint64_t T = (uint64_t)x * y;
+  uint32_t q = (uint32_t)T * mp;
+  uint32_t r = (uint32_t)((T + (uint64_t)q * M) >> 32);
+  return min(r, r - M);
+}
+
+// 2^32 mod M, M odd, 3 <= M < 2^31.
+__device__ __forceinline__ uint32_t mont_one32(uint32_t M) {
+  int bl = bitlen32(M);
+  uint32_t c = (1u << bl) - M;
+  for (int i = bl; i < 32; ++i) {
+    c <<= 1;
+    c = min(c, c - M);
+  }
+  return c;
+}
+
+// ---- limb vectors ---------------------------------------------------------
+
+template <int L>
+__device__ __forceinline__ void add_limbs(uint64_t (&acc)[L], const uint64_t (&t)[L]) {
+  uint64_t c = 0;
+#pragma unroll
+  for (int i = 0; i < L; ++i) acc[i] = __builtin_addcll(acc[i], t[i], c, (unsigned long long *)&c);
+}
+
+template <int L>
+__device__ __forceinline__ void neg_limbs(uint64_t (&x)[L]) {
+  uint64_t c = 0;
+#pragma unroll
+  for (int i = 0; i < L; ++i) x[i] = __builtin_subcll(0ull, x[i], c, (unsigned long long *)&c);
+}
+
+// t = -s * M^-1 mod 2^(64L): the L-limb quotient floor(r 2^(64L) / M) when
+// s = r 2^(64L) mod M (Hensel division, 64-bit limbs). h carries the part of
+// the dividend not yet divided; it stays below M.
+template <int L>
+__device__ __forceinline__ void hensel64(uint64_t s, uint64_t M, uint64_t mp, uint64_t (&t)[L]) {
+  uint64_t h = s;
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    uint64_t ti = h * mp;
+    h = __umul64hi(ti, M) + (h != 0u ? 1u : 0u);
+    t[i] = ti;
+  }
+}
+
+// The same with 32-bit limbs, for class-32 moduli (mp32 = -M^-1 mod 2^32).
+template <int L>
+__device__ __forceinline__ void hensel32(uint32_t s, uint32_t M, uint32_t mp32, uint64_t (&t)[L]) {
+  uint32_t h = s;
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    uint32_t lo = h * mp32;
+    h = __umulhi(lo, M) + (h != 0u ? 1u : 0u);
+    uint32_t hi = h * mp32;
+    h = __umulhi(hi, M) + (h != 0u ? 1u : 0u);
+    t[i] = ((uint64_t)hi << 32) | lo;
+  }
+}
+
+// Clear the low 64L-P bits (P <= 64L).
+template <int L>
+__device__ __forceinline__ void clip_low(uint64_t (&t)[L], uint32_t P) {
+  const uint32_t z = 64u * L - P;
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    const uint32_t lo = 64u * i;
+    if (z >= lo + 64u) t[i] = 0;
+    else if (z > lo) t[i] &= ~0ull << (z - lo);
+  }
+}
+
+}  // namespace pibbp

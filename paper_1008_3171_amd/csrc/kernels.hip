@@ -1,0 +1,403 @@
+// Kernels of the MI355X bit-extraction library.
+//
+//  head_kernel<L, ...>  the hot path: every head term (E >= 0, the A_k of
+//                       eq (3.3)) of every series range it is given. One
+//                       workgroup takes a chunk of 256*run consecutive k of
+//                       one series; each lane owns run indices of one parity
+//                       (so one sign), sums its terms, and the workgroup
+//                       folds the 256 lane sums into carry-save counters of
+//                       its query with 2L atomics.
+//  finalize_kernel<L>   one workgroup per query: the tail terms (the B_k of
+//                       eq (3.3)) up to each series' stop index, the
+//                       normalization of the carry-save counters, the
+//                       certification of section 3.1 and the output limbs.
+//
+// The split of the index set into series ranges, chunks, waves and lanes is
+// the multi-level partition of section 4 (jobs, tasks, threads) with the
+// GPU's own levels.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "arith.h"
+#include "plan.h"
+
+namespace pibbp {
+
+// Series tables as (negative sign?, c, a, b): the series contributes
+// sign * alt^k * 2^(d + c - step k) / (a k + b).
+// Bellard, eq (1.2): +2^2/(10k+1) -1/(10k+3) -2^-4/(10k+5) -2^-4/(10k+7)
+//                    +2^-6/(10k+9) -2^-1/(4k+1) -2^-6/(4k+3), times (-1)^k 2^-10k.
+// BBP in the form of eq (3.1): +2^2/(8k+1) -2^-1/(2k+1) -1/(8k+5) -2^-1/(4k+3),
+// times 2^-4k.
+struct DevSeries {
+  int32_t neg, c;
+  uint32_t a, b;
+};
+__constant__ DevSeries kSeries[2][7] = {
+    {{0, 2, 8, 1}, {1, -1, 2, 1}, {1, 0, 8, 5}, {1, -1, 4, 3}, {0, 0, 1, 1}, {0, 0, 1, 1}, {0, 0, 1, 1}},
+    {{0, 2, 10, 1}, {1, 0, 10, 3}, {1, -4, 10, 5}, {1, -4, 10, 7}, {0, -6, 10, 9}, {1, -1, 4, 1},
+     {1, -6, 4, 3}},
+};
+__constant__ int32_t kStep[2] = {4, 10};
+__constant__ int32_t kAlt[2] = {0, 1};
+__constant__ int32_t kNumSeries[2] = {4, 7};
+
+// ---- one term --------------------------------------------------------------
+
+// Head term at L limbs for a class-64 modulus: t = floor(r 2^(64L) / M) with
+// r = 2^E mod M, low bits above P cleared. nb >= bit length of
+// X = E + 64(L-1); extra leading zero bits only square the Montgomery one.
+template <int L>
+__device__ __forceinline__ void head_term64(uint64_t E, uint64_t M, uint32_t P, int nb,
+                                            uint64_t (&t)[L]) {
+  const uint64_t mp = neg_inv64(M);
+  uint64_t x = mont_one64(M);
+  const uint64_t X = E + 64ull * (L - 1);
+  for (int j = nb - 1; j >= 0; --j) x = sqr_redc64(x, (uint32_t)(X >> j) & 1u, M, mp);
+  x = x >= M ? x - M : x;  // s = 2^(E + 64L) mod M
+  hensel64<L>(x, M, mp, t);
+  clip_low<L>(t, P);
+}
+
+// Head term for a class-32 modulus (3 <= M < 2^31); X = E + 64L - 32.
+template <int L>
+__device__ __forceinline__ void head_term32(uint64_t E, uint32_t M, uint32_t P, int nb,
+                                            uint64_t (&t)[L]) {
+  const uint32_t mp = neg_inv32(M);
+  uint32_t x = mont_one32(M);
+  const uint64_t X = E + 64ull * L - 32ull;
+  for (int j = nb - 1; j >= 0; --j) x = sqr_redc32(x, (uint32_t)(X >> j) & 1u, M, mp);
+  hensel32<L>(x, M, mp, t);
+  clip_low<L>(t, P);
+}
+
+// ---- carry-save workgroup reduction -----------------------------------------
+
+// Adds the 256 lane values v (L limbs each, mod 2^(64L)) into 2L 64-bit
+// counters in carry-save form. The lane values are first summed exactly:
+// thread h adds up the 32-bit halves h of all lanes (below 2^40), then thread
+// 0 propagates the carries, so each counter receives one value below 2^32 per
+// call. The counters are exact while fewer than 2^32 calls add into them.
+template <int L>
+__device__ __forceinline__ void wg_fold(const uint64_t (&v)[L], uint32_t (*red)[256],
+                                        unsigned long long *sums,
+                                        unsigned long long *counters) {
+  const uint32_t tid = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    red[2 * i][tid] = (uint32_t)v[i];
+    red[2 * i + 1][tid] = (uint32_t)(v[i] >> 32);
+  }
+  __syncthreads();
+  if (tid < 2u * L) {
+    unsigned long long s = 0;
+    for (int i = 0; i < 256; ++i) s += red[tid][i];
+    sums[tid] = s;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long carry = 0;
+    for (int h = 0; h < 2 * L; ++h) {
+      const unsigned long long x = sums[h] + carry;
+      sums[h] = x & 0xffffffffull;
+      carry = x >> 32;
+    }
+  }
+  __syncthreads();
+  if (tid < 2u * L && sums[tid]) atomicAdd(&counters[tid], sums[tid]);
+  __syncthreads();
+}
+
+// ---- the head kernel ---------------------------------------------------------
+
+// The first active lane's value of x, as a wave-uniform scalar. readfirstlane
+// returns int: each half goes through uint32_t so it is not sign-extended.
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ const HeadSeg &find_seg(const HeadSeg *segs, int nseg, uint64_t ch) {
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].chunk0 <= ch) lo = mid;
+    else hi = mid - 1;
+  }
+  return segs[lo];
+}
+
+template <int L>
+__device__ void head_chunks(const HeadSeg *segs, int nseg, uint64_t nchunks, uint32_t run,
+                            unsigned long long *acc) {
+  __shared__ uint32_t red[2 * L][256];
+  __shared__ unsigned long long sums[2 * L];
+  const uint32_t tid = threadIdx.x;
+  const uint64_t CH = 256ull * run;
+  const uint32_t pair = tid >> 1, par = tid & 1u;
+  for (uint64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    const HeadSeg sg = find_seg(segs, nseg, ch);
+    const uint64_t kc = sg.kb + (ch - sg.chunk0) * CH;
+    const uint64_t kend = kc + CH < sg.ke ? kc + CH : sg.ke;
+    const DevSeries sr = kSeries[sg.formula][sg.j];
+    const int64_t step = kStep[sg.formula];
+    const uint64_t k0 = kc + 2ull * run * pair + par;
+    // every k of this lane has the parity of k0, so one sign for the chunk
+    const bool neg = (sr.neg != 0) ^ (kAlt[sg.formula] != 0 && (k0 & 1u));
+    const uint64_t dc = sg.d + (uint64_t)(int64_t)sr.c;
+    uint64_t sum[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) sum[i] = 0;
+    for (uint32_t i = 0; i < run; ++i) {
+      const uint64_t k = k0 + 2ull * i;
+      // lane 0 of a wave holds the wave's smallest k, hence its largest
+      // exponent: if it is past the range, the whole wave is.
+      const uint64_t kl0 = uniform64(k);
+      if (kl0 >= kend) break;
+      const bool active = k < kend;
+      const uint64_t kk = active ? k : kl0;
+      const uint64_t M = (uint64_t)sr.a * kk + sr.b;
+      const uint64_t E = dc - (uint64_t)step * kk;
+      const uint64_t E0 = dc - (uint64_t)step * kl0;
+      uint64_t t[L];
+      if (sg.cls == 64) {
+        const int nb = bitlen64(E0 + 64ull * (L - 1));
+        head_term64<L>(E, M, sg.P, nb, t);
+      } else {
+        const int nb = bitlen64(E0 + 64ull * L - 32ull);
+        const uint32_t M32 = M == 1 ? 3u : (uint32_t)M;  // 2^E mod 1 = 0: masked below
+        head_term32<L>(E, M32, sg.P, nb, t);
+      }
+      if (active && M != 1) add_limbs<L>(sum, t);
+    }
+    if (neg) neg_limbs<L>(sum);
+    wg_fold<L>(sum, red, sums, acc + (uint64_t)sg.query * 2u * L);
+  }
+}
+
+template <int L>
+__global__ __launch_bounds__(256) void head_kernel_args(HeadSegTable tab, uint64_t nchunks,
+                                                        uint32_t run, unsigned long long *acc) {
+  head_chunks<L>(tab.s, tab.n, nchunks, run, acc);
+}
+
+template <int L>
+__global__ __launch_bounds__(256) void head_kernel_ptr(const HeadSeg *segs, int nseg,
+                                                       uint64_t nchunks, uint32_t run,
+                                                       unsigned long long *acc) {
+  head_chunks<L>(segs, nseg, nchunks, run, acc);
+}
+
+__global__ void zero_kernel(unsigned long long *p, uint64_t n) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+// ---- tail terms and finalize ------------------------------------------------
+
+// Tail term (E < 0) at L limbs: floor(2^(64L+E) / M), low bits above P cleared.
+// For M > 1 it is floor(2^(64L)/M) shifted right by -E (the same floor), and
+// floor(2^(64L)/M) is the head formula with E = 0 (r = 1).
+template <int L>
+__device__ void tail_term(int64_t E, uint64_t M, uint32_t P, uint64_t (&t)[L]) {
+  const int64_t e = 64ll * L + E;
+#pragma unroll
+  for (int i = 0; i < L; ++i) t[i] = 0;
+  if (e < 0) return;
+  if (M == 1) {
+    const int li = (int)(e >> 6);
+#pragma unroll
+    for (int i = 0; i < L; ++i)
+      if (i == li) t[i] = 1ull << (e & 63);
+  } else {
+    uint64_t full[L];
+    head_term64<L>(0, M, 64u * L, bitlen64(64ull * (L - 1)), full);
+    const int sh = (int)(-E);
+    const int ls = sh >> 6, bs = sh & 63;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      uint64_t lo = 0, hi = 0;
+#pragma unroll
+      for (int s = 0; s < L; ++s) {
+        if (s == i + ls) lo = full[s];
+        if (s == i + ls + 1) hi = full[s];
+      }
+      t[i] = bs ? (lo >> bs) | (hi << (64 - bs)) : lo;
+    }
+  }
+  clip_low<L>(t, P);
+}
+
+template <int L>
+__global__ __launch_bounds__(256) void finalize_kernel(FinQuery single, const FinQuery *qs,
+                                                       const unsigned long long *acc,
+                                                       uint64_t *out, pi_status *status) {
+  __shared__ uint32_t red[2 * L][256];
+  __shared__ unsigned long long cnt[2 * L];
+  __shared__ unsigned long long nz_total;
+  const uint32_t tid = threadIdx.x;
+  const FinQuery q = qs ? qs[blockIdx.x] : single;
+  const int f = (int)q.formula;
+  const int J = kNumSeries[f];
+  const int64_t step = kStep[f];
+  if (tid == 0) nz_total = 0;
+  uint64_t ntail = 0;
+  for (int j = 0; j < J; ++j) ntail += q.tk1[j] - q.tk0[j];
+  uint64_t sum[L];
+#pragma unroll
+  for (int i = 0; i < L; ++i) sum[i] = 0;
+  unsigned long long nz = 0;
+  // tail items of all series, flattened; a few hundred at most
+  for (uint64_t it = tid; it < ntail; it += 256) {
+    uint64_t r = it;
+    int j = 0;
+    while (r >= q.tk1[j] - q.tk0[j]) {
+      r -= q.tk1[j] - q.tk0[j];
+      ++j;
+    }
+    const uint64_t k = q.tk0[j] + r;
+    const DevSeries sr = kSeries[f][j];
+    const int64_t E = (int64_t)q.d + sr.c - step * (int64_t)k;
+    const uint64_t M = (uint64_t)sr.a * k + sr.b;
+    uint64_t t[L];
+    tail_term<L>(E, M, q.P, t);
+    bool nonzero = false;
+#pragma unroll
+    for (int i = 0; i < L; ++i) nonzero |= t[i] != 0;
+    nz += nonzero ? 1u : 0u;
+    const bool neg = (sr.neg != 0) ^ (kAlt[f] != 0 && (k & 1u));
+    if (neg) neg_limbs<L>(t);
+    add_limbs<L>(sum, t);
+  }
+  if (tid < 2u * L) cnt[tid] = acc[(uint64_t)blockIdx.x * 2u * L + tid];
+  __syncthreads();
+  if (nz) atomicAdd(&nz_total, nz);
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    red[2 * i][tid] = (uint32_t)sum[i];
+    red[2 * i + 1][tid] = (uint32_t)(sum[i] >> 32);
+  }
+  __syncthreads();
+  if (tid < 2u * L) {
+    unsigned long long s = cnt[tid];
+    for (int i = 0; i < 256; ++i) s += red[tid][i];
+    cnt[tid] = s;
+  }
+  __syncthreads();
+  if (tid != 0) return;
+  // normalize the carry-save counters: S = sum_h cnt[h] 2^(32h) mod 2^(64L)
+  uint64_t S[PI_MAX_L];
+  unsigned long long carry = 0;
+  for (int i = 0; i < L; ++i) {
+    const unsigned long long lo = cnt[2 * i] + carry;
+    carry = (lo >> 32) + (lo < carry ? (1ull << 32) : 0ull);
+    const unsigned long long hi = cnt[2 * i + 1] + carry;
+    carry = (hi >> 32) + (hi < carry ? (1ull << 32) : 0ull);
+    S[i] = (lo & 0xffffffffull) | (hi << 32);
+  }
+  // the query's result is the top Lq limbs (the lower L - Lq are zero)
+  const int Lq = (int)q.Lq;
+  const uint64_t *Sq = S + (L - Lq);
+  uint64_t *o = out + q.out_off;
+  for (int i = 0; i < Lq; ++i) o[i] = Sq[i];
+  if (!q.want_status) return;
+  // Certification (section 3.1, adapted to truncated terms). S is
+  // left-aligned: z = 64Lq - P zero bits at the bottom. G = the low
+  // g = 64Lq - w bits, B = (N + 2J) 2^z; certified iff G >= B and
+  // G + B <= 2^g. Both sides are compared over Lq + 1 limbs.
+  const uint64_t N = q.nhead + nz_total;
+  const uint32_t z = 64u * (uint32_t)Lq - q.P, g = 64u * (uint32_t)Lq - q.w;
+  const uint64_t Bn = N + 2ull * (uint64_t)J;
+  uint64_t Bv[PI_MAX_L + 1], Gv[PI_MAX_L + 1], Sum[PI_MAX_L + 1], Pg[PI_MAX_L + 1];
+  for (int i = 0; i <= Lq; ++i) {
+    Bv[i] = 0;
+    Pg[i] = 0;
+    const uint32_t lo = 64u * (uint32_t)i;
+    uint64_t gi = 0;
+    if (i < Lq) gi = g >= lo + 64u ? Sq[i] : (g > lo ? Sq[i] & ((1ull << (g - lo)) - 1ull) : 0ull);
+    Gv[i] = gi;
+    if (g >= lo && g < lo + 64u) Pg[i] = 1ull << (g - lo);
+  }
+  Bv[0] = Bn << z;
+  if (z) Bv[1] = Bn >> (64u - z);
+  unsigned long long c1 = 0, c2 = 0, c3 = 0;
+  for (int i = 0; i <= Lq; ++i) {
+    (void)__builtin_subcll(Gv[i], Bv[i], c1, &c1);      // G - B: borrow out => G < B
+    Sum[i] = __builtin_addcll(Gv[i], Bv[i], c2, &c2);  // G + B
+  }
+  for (int i = 0; i <= Lq; ++i) (void)__builtin_subcll(Pg[i], Sum[i], c3, &c3);  // 2^g - (G+B)
+  const bool ok = c1 == 0 && c2 == 0 && c3 == 0;
+  pi_status st;
+  st.code = ok ? PI_OK : PI_UNCERTAIN;
+  st.reserved = 0;
+  st.nterms = N;
+  status[q.status_idx] = st;
+}
+
+// ---- launchers ---------------------------------------------------------------
+
+template <int L>
+static hipError_t launch_head_args_L(const HeadSegTable &tab, uint64_t nchunks, uint32_t run,
+                                     int grid, unsigned long long *acc, hipStream_t st) {
+  hipLaunchKernelGGL(head_kernel_args<L>, dim3(grid), dim3(256), 0, st, tab, nchunks, run, acc);
+  return hipGetLastError();
+}
+template <int L>
+static hipError_t launch_head_ptr_L(const HeadSeg *segs, int nseg, uint64_t nchunks, uint32_t run,
+                                    int grid, unsigned long long *acc, hipStream_t st) {
+  hipLaunchKernelGGL(head_kernel_ptr<L>, dim3(grid), dim3(256), 0, st, segs, nseg, nchunks, run,
+                     acc);
+  return hipGetLastError();
+}
+template <int L>
+static hipError_t launch_fin_L(const FinQuery &single, const FinQuery *qs, int nq,
+                               const unsigned long long *acc, uint64_t *out, pi_status *status,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(finalize_kernel<L>, dim3(nq), dim3(256), 0, st, single, qs, acc, out, status);
+  return hipGetLastError();
+}
+
+#define PIBBP_DISPATCH(Lk, CALL)                     \
+  switch (Lk) {                                      \
+    case 1: return CALL(1);                          \
+    case 2: return CALL(2);                          \
+    case 3: return CALL(3);                          \
+    case 4: return CALL(4);                          \
+    case 5: return CALL(5);                          \
+    case 6: return CALL(6);                          \
+    case 8: return CALL(8);                          \
+    case 12: return CALL(12);                        \
+    case 17: return CALL(17);                        \
+    default: return hipErrorInvalidValue;            \
+  }
+
+hipError_t launch_head_args(int Lk, const HeadSegTable &tab, uint64_t nchunks, uint32_t run,
+                            int grid, unsigned long long *acc, hipStream_t st) {
+#define C(L) launch_head_args_L<L>(tab, nchunks, run, grid, acc, st)
+  PIBBP_DISPATCH(Lk, C)
+#undef C
+}
+hipError_t launch_head_ptr(int Lk, const HeadSeg *segs, int nseg, uint64_t nchunks, uint32_t run,
+                           int grid, unsigned long long *acc, hipStream_t st) {
+#define C(L) launch_head_ptr_L<L>(segs, nseg, nchunks, run, grid, acc, st)
+  PIBBP_DISPATCH(Lk, C)
+#undef C
+}
+hipError_t launch_finalize(int Lk, const FinQuery &single, const FinQuery *qs, int nq,
+                           const unsigned long long *acc, uint64_t *out, pi_status *status,
+                           hipStream_t st) {
+#define C(L) launch_fin_L<L>(single, qs, nq, acc, out, status, st)
+  PIBBP_DISPATCH(Lk, C)
+#undef C
+}
+hipError_t launch_zero(unsigned long long *p, uint64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  int grid = (int)((n + 255) / 256);
+  if (grid > 1024) grid = 1024;
+  hipLaunchKernelGGL(zero_kernel, dim3(grid), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace pibbp

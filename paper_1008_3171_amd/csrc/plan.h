@@ -1,0 +1,51 @@
+// Work descriptors passed from the host planner to the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pibbp.h"
+
+namespace pibbp {
+
+constexpr int PI_MAX_L = 17;          // ceil(PI_MAX_P / 64)
+constexpr int kMaxArgSegs = 14;       // 7 series x 2 modulus classes
+
+// A range [kb, ke) of head indices (E >= 0) of series j of one query, all of
+// one modulus class; its chunks are numbered chunk0, chunk0 + 1, ...
+struct HeadSeg {
+  uint64_t kb, ke;
+  uint64_t chunk0;
+  uint64_t d;          // n - 1
+  uint32_t formula, j, P, query;
+  uint32_t cls;        // 32: M < 2^31, 64: 2^31 <= M < 2^60
+  uint32_t pad;
+};
+
+// Segments of a single query, passed by value as a kernel argument.
+struct HeadSegTable {
+  HeadSeg s[kMaxArgSegs];
+  int32_t n;
+  int32_t pad;
+};
+
+// What the finalize kernel needs for one query: the tail index range of each
+// series, the head term count, and where to write.
+struct FinQuery {
+  uint64_t d;
+  uint64_t nhead;      // head indices summed (N before the tail)
+  uint64_t out_off;    // in limbs
+  uint64_t tk0[7], tk1[7];
+  uint32_t formula, P, w, Lq;
+  uint32_t want_status, status_idx;
+};
+
+hipError_t launch_head_args(int Lk, const HeadSegTable &tab, uint64_t nchunks, uint32_t run,
+                            int grid, unsigned long long *acc, hipStream_t st);
+hipError_t launch_head_ptr(int Lk, const HeadSeg *segs, int nseg, uint64_t nchunks, uint32_t run,
+                           int grid, unsigned long long *acc, hipStream_t st);
+hipError_t launch_finalize(int Lk, const FinQuery &single, const FinQuery *qs, int nq,
+                           const unsigned long long *acc, uint64_t *out, pi_status *status,
+                           hipStream_t st);
+hipError_t launch_zero(unsigned long long *p, uint64_t n, hipStream_t st);
+
+}  // namespace pibbp

@@ -1,0 +1,64 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every function
+include/pibbp.h declares, and rejects bad arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+import paper_1008_3171_amd as pb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "pibbp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(pi_[a-z_0-9]+)\s*\(",
+                                 src, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pb.load()
+    names = declared_functions()
+    assert {"pi_extract", "pi_extract_ex", "pi_sum_slice", "pi_extract_batch",
+            "pi_workspace_size", "pi_strerror"} <= set(names)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_strerror():
+    lib = pb.load()
+    for code in (0, 1, -1, -2, -3, -4, 99):
+        assert lib.pi_strerror(code)
+
+
+@pytest.mark.parametrize("formula", [pb.BBP, pb.BELLARD])
+def test_head_term_count_matches_oracle_tables(formula):
+    rows, step, _ = oracle.series_table(formula)
+    for n in (1, 2, 7, 9, 100, 10 ** 6, 10 ** 10 + 1, 10 ** 12, 2 * 10 ** 15 - 3):
+        d = n - 1
+        want = sum(max(0, (d + c) // step + 1) for _, c, _, _ in rows)
+        assert pb.head_terms(formula, n) == want
+    if formula == pb.BELLARD:
+        assert pb.head_terms(formula, 10 ** 6) == 700001
+
+
+def test_invalid_arguments_are_rejected_synchronously():
+    lib = pb.load()
+    dummy = ctypes.c_void_p(16)   # never dereferenced: validation fails first
+    null = ctypes.c_void_p(0)
+    E = -1
+    assert lib.pi_extract_ex(2, 10, 8, 72, dummy, null, null) == E          # formula
+    assert lib.pi_extract_ex(1, 0, 8, 72, dummy, null, null) == E           # n = 0
+    assert lib.pi_extract_ex(1, 10, 0, 72, dummy, null, null) == E          # nbits = 0
+    assert lib.pi_extract_ex(1, 10, 80, 72, dummy, null, null) == E         # P < nbits
+    assert lib.pi_extract_ex(1, 10, 8, 2000, dummy, null, null) == E        # P > max
+    assert lib.pi_extract_ex(1, 10, 8, 72, null, null, null) == E           # out = NULL
+    assert lib.pi_sum_slice(pb.term_id(1, 7), 10, 0, 5, 64, dummy, null) == E
+    assert lib.pi_sum_slice(pb.term_id(0, 4), 10, 0, 5, 64, dummy, null) == E
+    assert lib.pi_sum_slice(pb.term_id(1, 0), 10, 6, 5, 64, dummy, null) == E  # k0 > k1
+    assert lib.pi_extract(1, 10, 0, dummy, null) == E
+    # moduli past 2^60 are outside the supported range
+    assert lib.pi_extract_ex(1, 2 ** 61, 8, 72, dummy, null, null) == -4
