@@ -42,12 +42,13 @@ def series(formula):
 def mul32_per_launch(formula, n, P):
     """Algorithmic 32-bit multiplies of every head term of one extraction.
 
-    Per term with a modulus of class 64 (R = 2^64): bitlen(X) Montgomery
-    squarings of a two-word residue, X = E + 64(L-1), at 11 multiplies each
-    (4 for the product, 3 for q = T m' mod 2^64, 4 for the high half of qM);
-    12 for -M^-1 mod 2^64; 7 per limb of the Hensel division. Class 32
-    (M < 2^31, R = 2^32): 3 per squaring (X = E + 64L - 32), 6 for the
-    inverse, 4 per limb.
+    Class 62 (2^31 <= M, R = 2^62, two 31-bit digits): bitlen(X) Montgomery
+    squarings, X = E + 64L - 62, at 9 multiplies each (3 for the square,
+    2 reduction digits, 4 digit-by-modulus products); 12 for -M^-1 mod 2^64;
+    2 for the starting value 2^62 - qM; 7 per limb of the Hensel division
+    (3 for the low product, 4 for the high half of t M).
+    Class 32 (M < 2^31, R = 2^32): 3 per squaring (X = E + 64L - 32), 6 for
+    the inverse, 4 per 64-bit limb of the division.
     """
     rows, step = series(formula)
     L = (P + 63) // 64
@@ -59,11 +60,11 @@ def mul32_per_launch(formula, n, P):
             continue
         K = (d + c) // step + 1
         ks = min(K, max(0, -(-(CLASS32_LIMIT - b) // a)))
-        for lo, hi, cls in ((0, ks, 32), (ks, K, 64)):
+        for lo, hi, cls in ((0, ks, 32), (ks, K, 62)):
             if lo >= hi:
                 continue
-            off = 64 * (L - 1) if cls == 64 else 64 * L - 32
-            per_sq, fixed = (11, 12 + 7 * L) if cls == 64 else (3, 6 + 4 * L)
+            off = 64 * L - 62 if cls == 62 else 64 * L - 32
+            per_sq, fixed = (9, 14 + 7 * L) if cls == 62 else (3, 6 + 4 * L)
             # X(k) = d + c - step k + off decreases with k; sum bitlen over bands
             k = lo
             while k < hi:

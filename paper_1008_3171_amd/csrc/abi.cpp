@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <mutex>
 #include <utility>
@@ -37,7 +38,7 @@ const int kHJ[2] = {4, 7};
 const int kLimbClasses[] = {1, 2, 3, 4, 5, 6, 8, 12, 17};
 
 constexpr uint64_t kClass32Limit = 1ull << 31;
-constexpr uint64_t kModulusLimit = 1ull << 60;
+constexpr uint64_t kModulusLimit = 1ull << 58;
 
 int limb_class(uint32_t P) {
   const int Lq = (int)((P + 63u) / 64u);
@@ -218,21 +219,46 @@ int resident_grid() {
 
 int hip_err(hipError_t e) { return e == hipSuccess ? PI_OK : PI_EDEVICE; }
 
+// Largest run (indices per lane per chunk) a class-62 segment with moduli in
+// [Mmin, Mmax] and modulus step a allows. A lane's ladder starts from
+// g = 2^62 - qM with q = floor(2^62/M_last), so g < (e+1)M with
+// e <= 2^62 2a run / M^2 + 1; the first squaring needs (e+1)^2 M < 2^62.
+// f(M) = (2^63 a run / M^2 + 2)^2 M is convex, so checking both ends of the
+// modulus range suffices; a factor 2 of margin covers rounding here.
+uint32_t safe_run62(uint32_t run, uint64_t Mmin, uint64_t Mmax, uint64_t a) {
+  auto ok = [&](double r) {
+    const double A = std::ldexp((double)a * r, 63);
+    for (double M : {(double)Mmin, (double)Mmax}) {
+      const double e2 = A / (M * M) + 2.0;
+      if (e2 * e2 * M >= std::ldexp(1.0, 61)) return false;
+    }
+    return true;
+  };
+  while (run > 1 && !ok((double)run)) run = std::max<uint32_t>(1, run / 2);
+  return run;
+}
+
+// Number the chunks of the segments and fix each segment's run.
+uint64_t number_chunks(std::vector<HeadSeg> &segs, uint32_t run) {
+  uint64_t nchunks = 0;
+  for (HeadSeg &g : segs) {
+    const HostSeries &s = kHSeries[g.formula][g.j];
+    g.run = g.cls == 64 ? safe_run62(run, s.a * g.kb + s.b, s.a * (g.ke - 1) + s.b, s.a) : run;
+    g.chunk0 = nchunks;
+    nchunks += (g.ke - g.kb + 256ull * g.run - 1) / (256ull * g.run);
+  }
+  return nchunks;
+}
+
 // Launch everything for one planned query (head segments passed by value).
 int run_single(const QueryPlan &qp, uint64_t *out, pi_status *status, hipStream_t st) {
   std::vector<HeadSeg> segs;
   head_segments(qp, 0, segs);
   const int grid_max = resident_grid();
-  const uint32_t run = pick_run(qp.nhead, grid_max);
-  const uint64_t CH = 256ull * run;
+  const uint64_t nchunks = number_chunks(segs, pick_run(qp.nhead, grid_max));
   HeadSegTable tab;
   memset(&tab, 0, sizeof tab);
-  uint64_t nchunks = 0;
-  for (size_t i = 0; i < segs.size(); ++i) {
-    segs[i].chunk0 = nchunks;
-    nchunks += (segs[i].ke - segs[i].kb + CH - 1) / CH;
-    tab.s[i] = segs[i];
-  }
+  for (size_t i = 0; i < segs.size(); ++i) tab.s[i] = segs[i];
   tab.n = (int)segs.size();
   const int Lk = qp.Lk;
   int err = PI_OK;
@@ -241,7 +267,7 @@ int run_single(const QueryPlan &qp, uint64_t *out, pi_status *status, hipStream_
   if (int e = hip_err(launch_zero(acc, 2u * (uint64_t)Lk, st))) return e;
   if (nchunks) {
     const int grid = (int)std::min<uint64_t>(nchunks, (uint64_t)grid_max);
-    if (int e = hip_err(launch_head_args(Lk, tab, nchunks, run, grid, acc, st))) return e;
+    if (int e = hip_err(launch_head_args(Lk, tab, nchunks, grid, acc, st))) return e;
   }
   FinQuery fq = fin_query(qp, 0, status != nullptr, 0);
   return hip_err(launch_finalize(Lk, fq, nullptr, 1, acc, out, status, st));
@@ -307,7 +333,7 @@ const char *pi_strerror(int code) {
     case PI_EINVAL: return "invalid argument";
     case PI_ENOMEM: return "out of device memory";
     case PI_EDEVICE: return "HIP runtime or device error";
-    case PI_EUNSUPPORTED: return "outside the supported range (modulus >= 2^60 or n too large)";
+    case PI_EUNSUPPORTED: return "outside the supported range (modulus >= 2^58 or n too large)";
     default: return "unknown error code";
   }
 }

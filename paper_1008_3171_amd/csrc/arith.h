@@ -79,6 +79,53 @@ __device__ __forceinline__ uint64_t mont_one64(uint64_t M) {
   return c;
 }
 
+// ---- class 62: R = 2^62, residues in two 31-bit digits, M < 2^58 ---------
+//
+// x = d0 + d1 2^31 with d0 < 2^31. Every partial product is below 2^62 and
+// every column sum below 2^64, so no carry ever has to be tracked: the
+// reduction digit u = (column mod 2^31) * (-M^-1) mod 2^31 clears the low 31
+// bits and the column shifted right by 31 feeds the next one.
+
+constexpr uint32_t kMask31 = 0x7fffffffu;
+
+// x <- 2^b * REDC(x^2) = 2^b x^2 2^-62 (mod M), for x < 4M, b in {0, 1}.
+// Bounds: d1 < 2^29, so c0 < 2^63, c1 < 2^63, c2 < 2^60; REDC(x^2) <
+// 16M^2/2^62 + M <= 2M for M <= 2^58, and after the doubling x < 4M again.
+__device__ __forceinline__ void sqr_redc62(uint32_t &d0, uint32_t &d1, uint32_t b, uint32_t m0,
+                                           uint32_t m1, uint32_t p) {
+  uint64_t c0 = (uint64_t)d0 * d0;
+  const uint32_t u0 = ((uint32_t)c0 * p) & kMask31;
+  c0 += (uint64_t)u0 * m0;
+  uint64_t c1 = (uint64_t)d0 * (d1 << 1) + (c0 >> 31);
+  c1 += (uint64_t)u0 * m1;
+  const uint32_t u1 = ((uint32_t)c1 * p) & kMask31;
+  c1 += (uint64_t)u1 * m0;
+  uint64_t c2 = (uint64_t)d1 * d1 + (c1 >> 31);
+  c2 += (uint64_t)u1 * m1;
+  c2 <<= b;
+  d0 = (uint32_t)c2 & kMask31;
+  d1 = (uint32_t)(c2 >> 31);
+}
+
+// floor(2^62 / M) for 2^31 <= M < 2^58, by restoring long division: the
+// quotient has at most 32 bits, and bit s is tried only while M 2^s stays
+// below 2^64.
+__device__ __forceinline__ uint32_t div_2_62(uint64_t M) {
+  const int room = 63 - bitlen64(M);  // largest s with M << s < 2^63
+  uint64_t r = 1ull << 62;
+  uint32_t q = 0;
+  for (int s = 31; s >= 0; --s) {
+    if (s <= room) {
+      const uint64_t ms = M << s;
+      if (r >= ms) {
+        r -= ms;
+        q |= 1u << s;
+      }
+    }
+  }
+  return q;
+}
+
 // ---- class 32: R = 2^32, residues in [0, M), M < 2^31 --------------------
 
 // x^2 2^b 2^-32 mod M for x < M: T = x (x << b) < 2M^2 and qM < 2^63, so

@@ -128,20 +128,90 @@ __device__ __forceinline__ const HeadSeg &find_seg(const HeadSeg *segs, int nseg
   return segs[lo];
 }
 
+// Class-62 terms of one lane: k = k0, k0 + 2, ..., k0 + 2(run-1) (one
+// parity, so one sign), accumulated unsigned into sum. M and the ladder
+// exponent X = E + 64L - 62 step by 2a and -2 step.
+//
+// The ladder starts from an unreduced Montgomery one g = 2^62 - qM, with
+// q = floor(2^62 / M_last) computed once for the run (M_last its largest
+// modulus), so g == 2^62 (mod M) and 0 <= g < (e+1)M with
+// e = floor(2^62/M) - q. The host sizes runs so that (e+1)^2 M < 2^62, which
+// keeps the first squaring inside its bound; after it the residue is below 4M.
 template <int L>
-__device__ void head_chunks(const HeadSeg *segs, int nseg, uint64_t nchunks, uint32_t run,
+__device__ __forceinline__ void lane_run62(uint64_t k0, uint32_t run, uint64_t kend, uint64_t a,
+                                           uint64_t b, uint64_t dc, uint64_t step, uint32_t P,
+                                           uint64_t (&sum)[L]) {
+  const uint64_t dM = 2u * a, dX = 2u * step;
+  uint64_t M = a * k0 + b;
+  uint64_t X = dc + 64ull * L - 62ull - step * k0;
+  const uint32_t q = div_2_62(M + dM * (run - 1u));
+  for (uint32_t i = 0; i < run; ++i, M += dM, X -= dX) {
+    const uint64_t k = k0 + 2ull * i;
+    // lane 0 holds the wave's smallest k, so the largest exponent: if it is
+    // past the chunk, so is every lane, and its X bounds the ladder length.
+    if (uniform64(k) >= kend) break;
+    const int nb = bitlen64(uniform64(X));
+    const uint64_t mp = neg_inv64(M);
+    const uint32_t m0 = (uint32_t)M & kMask31, m1 = (uint32_t)(M >> 31);
+    const uint32_t p = (uint32_t)mp & kMask31;
+    const uint64_t g = (1ull << 62) - (uint64_t)q * M;
+    uint32_t d0 = (uint32_t)g & kMask31, d1 = (uint32_t)(g >> 31);
+    const uint32_t xl = (uint32_t)X, xh = (uint32_t)(X >> 32);
+    for (int j = nb - 33; j >= 0; --j) sqr_redc62(d0, d1, (xh >> j) & 1u, m0, m1, p);
+    for (int j = (nb < 32 ? nb : 32) - 1; j >= 0; --j) sqr_redc62(d0, d1, (xl >> j) & 1u, m0, m1, p);
+    uint64_t x = d0 + ((uint64_t)d1 << 31);  // 2^(E + 64L) mod M, below 4M
+    x = x >= 2u * M ? x - 2u * M : x;
+    x = x >= M ? x - M : x;
+    uint64_t t[L];
+    hensel64<L>(x, M, mp, t);
+    clip_low<L>(t, P);
+    if (k < kend) add_limbs<L>(sum, t);
+  }
+}
+
+// Class-32 terms of one lane (3 <= M < 2^31, except the M = 1 term of k = 0,
+// whose value 2^E mod 1 = 0 is skipped); X = E + 64L - 32.
+template <int L>
+__device__ __forceinline__ void lane_run32(uint64_t k0, uint32_t run, uint64_t kend, uint64_t a,
+                                           uint64_t b, uint64_t dc, uint64_t step, uint32_t P,
+                                           uint64_t (&sum)[L]) {
+  for (uint32_t i = 0; i < run; ++i) {
+    const uint64_t k = k0 + 2ull * i;
+    const uint64_t kl0 = uniform64(k);
+    if (kl0 >= kend) break;
+    const bool active = k < kend;
+    const uint64_t kk = active ? k : kl0;
+    const uint64_t M = a * kk + b;
+    const uint64_t X = dc - step * kk + 64ull * L - 32ull;
+    const int nb = bitlen64(dc - step * kl0 + 64ull * L - 32ull);
+    const uint32_t M32 = M == 1 ? 3u : (uint32_t)M;
+    const uint32_t mp = neg_inv32(M32);
+    uint32_t x = mont_one32(M32);
+    const uint32_t xl = (uint32_t)X, xh = (uint32_t)(X >> 32);
+    for (int j = nb - 33; j >= 0; --j) x = sqr_redc32(x, (xh >> j) & 1u, M32, mp);
+    for (int j = (nb < 32 ? nb : 32) - 1; j >= 0; --j) x = sqr_redc32(x, (xl >> j) & 1u, M32, mp);
+    uint64_t t[L];
+    hensel32<L>(x, M32, mp, t);
+    clip_low<L>(t, P);
+    if (active && M != 1) add_limbs<L>(sum, t);
+  }
+}
+
+template <int L>
+__device__ void head_chunks(const HeadSeg *segs, int nseg, uint64_t nchunks,
                             unsigned long long *acc) {
   __shared__ uint32_t red[2 * L][256];
   __shared__ unsigned long long sums[2 * L];
   const uint32_t tid = threadIdx.x;
-  const uint64_t CH = 256ull * run;
   const uint32_t pair = tid >> 1, par = tid & 1u;
   for (uint64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
     const HeadSeg sg = find_seg(segs, nseg, ch);
+    const uint32_t run = sg.run;
+    const uint64_t CH = 256ull * run;
     const uint64_t kc = sg.kb + (ch - sg.chunk0) * CH;
     const uint64_t kend = kc + CH < sg.ke ? kc + CH : sg.ke;
     const DevSeries sr = kSeries[sg.formula][sg.j];
-    const int64_t step = kStep[sg.formula];
+    const uint64_t step = (uint64_t)kStep[sg.formula];
     const uint64_t k0 = kc + 2ull * run * pair + par;
     // every k of this lane has the parity of k0, so one sign for the chunk
     const bool neg = (sr.neg != 0) ^ (kAlt[sg.formula] != 0 && (k0 & 1u));
@@ -149,28 +219,10 @@ __device__ void head_chunks(const HeadSeg *segs, int nseg, uint64_t nchunks, uin
     uint64_t sum[L];
 #pragma unroll
     for (int i = 0; i < L; ++i) sum[i] = 0;
-    for (uint32_t i = 0; i < run; ++i) {
-      const uint64_t k = k0 + 2ull * i;
-      // lane 0 of a wave holds the wave's smallest k, hence its largest
-      // exponent: if it is past the range, the whole wave is.
-      const uint64_t kl0 = uniform64(k);
-      if (kl0 >= kend) break;
-      const bool active = k < kend;
-      const uint64_t kk = active ? k : kl0;
-      const uint64_t M = (uint64_t)sr.a * kk + sr.b;
-      const uint64_t E = dc - (uint64_t)step * kk;
-      const uint64_t E0 = dc - (uint64_t)step * kl0;
-      uint64_t t[L];
-      if (sg.cls == 64) {
-        const int nb = bitlen64(E0 + 64ull * (L - 1));
-        head_term64<L>(E, M, sg.P, nb, t);
-      } else {
-        const int nb = bitlen64(E0 + 64ull * L - 32ull);
-        const uint32_t M32 = M == 1 ? 3u : (uint32_t)M;  // 2^E mod 1 = 0: masked below
-        head_term32<L>(E, M32, sg.P, nb, t);
-      }
-      if (active && M != 1) add_limbs<L>(sum, t);
-    }
+    if (sg.cls == 64)
+      lane_run62<L>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum);
+    else
+      lane_run32<L>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum);
     if (neg) neg_limbs<L>(sum);
     wg_fold<L>(sum, red, sums, acc + (uint64_t)sg.query * 2u * L);
   }
@@ -178,15 +230,14 @@ __device__ void head_chunks(const HeadSeg *segs, int nseg, uint64_t nchunks, uin
 
 template <int L>
 __global__ __launch_bounds__(256) void head_kernel_args(HeadSegTable tab, uint64_t nchunks,
-                                                        uint32_t run, unsigned long long *acc) {
-  head_chunks<L>(tab.s, tab.n, nchunks, run, acc);
+                                                        unsigned long long *acc) {
+  head_chunks<L>(tab.s, tab.n, nchunks, acc);
 }
 
 template <int L>
 __global__ __launch_bounds__(256) void head_kernel_ptr(const HeadSeg *segs, int nseg,
-                                                       uint64_t nchunks, uint32_t run,
-                                                       unsigned long long *acc) {
-  head_chunks<L>(segs, nseg, nchunks, run, acc);
+                                                       uint64_t nchunks, unsigned long long *acc) {
+  head_chunks<L>(segs, nseg, nchunks, acc);
 }
 
 __global__ void zero_kernel(unsigned long long *p, uint64_t n) {
@@ -339,16 +390,15 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinQuery single, const Fi
 // ---- launchers ---------------------------------------------------------------
 
 template <int L>
-static hipError_t launch_head_args_L(const HeadSegTable &tab, uint64_t nchunks, uint32_t run,
-                                     int grid, unsigned long long *acc, hipStream_t st) {
-  hipLaunchKernelGGL(head_kernel_args<L>, dim3(grid), dim3(256), 0, st, tab, nchunks, run, acc);
+static hipError_t launch_head_args_L(const HeadSegTable &tab, uint64_t nchunks, int grid,
+                                     unsigned long long *acc, hipStream_t st) {
+  hipLaunchKernelGGL(head_kernel_args<L>, dim3(grid), dim3(256), 0, st, tab, nchunks, acc);
   return hipGetLastError();
 }
 template <int L>
-static hipError_t launch_head_ptr_L(const HeadSeg *segs, int nseg, uint64_t nchunks, uint32_t run,
-                                    int grid, unsigned long long *acc, hipStream_t st) {
-  hipLaunchKernelGGL(head_kernel_ptr<L>, dim3(grid), dim3(256), 0, st, segs, nseg, nchunks, run,
-                     acc);
+static hipError_t launch_head_ptr_L(const HeadSeg *segs, int nseg, uint64_t nchunks, int grid,
+                                    unsigned long long *acc, hipStream_t st) {
+  hipLaunchKernelGGL(head_kernel_ptr<L>, dim3(grid), dim3(256), 0, st, segs, nseg, nchunks, acc);
   return hipGetLastError();
 }
 template <int L>
@@ -373,15 +423,15 @@ static hipError_t launch_fin_L(const FinQuery &single, const FinQuery *qs, int n
     default: return hipErrorInvalidValue;            \
   }
 
-hipError_t launch_head_args(int Lk, const HeadSegTable &tab, uint64_t nchunks, uint32_t run,
-                            int grid, unsigned long long *acc, hipStream_t st) {
-#define C(L) launch_head_args_L<L>(tab, nchunks, run, grid, acc, st)
+hipError_t launch_head_args(int Lk, const HeadSegTable &tab, uint64_t nchunks, int grid,
+                            unsigned long long *acc, hipStream_t st) {
+#define C(L) launch_head_args_L<L>(tab, nchunks, grid, acc, st)
   PIBBP_DISPATCH(Lk, C)
 #undef C
 }
-hipError_t launch_head_ptr(int Lk, const HeadSeg *segs, int nseg, uint64_t nchunks, uint32_t run,
-                           int grid, unsigned long long *acc, hipStream_t st) {
-#define C(L) launch_head_ptr_L<L>(segs, nseg, nchunks, run, grid, acc, st)
+hipError_t launch_head_ptr(int Lk, const HeadSeg *segs, int nseg, uint64_t nchunks, int grid,
+                           unsigned long long *acc, hipStream_t st) {
+#define C(L) launch_head_ptr_L<L>(segs, nseg, nchunks, grid, acc, st)
   PIBBP_DISPATCH(Lk, C)
 #undef C
 }

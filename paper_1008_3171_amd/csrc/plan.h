@@ -17,8 +17,8 @@ struct HeadSeg {
   uint64_t chunk0;
   uint64_t d;          // n - 1
   uint32_t formula, j, P, query;
-  uint32_t cls;        // 32: M < 2^31, 64: 2^31 <= M < 2^60
-  uint32_t pad;
+  uint32_t cls;        // 32: M < 2^31 (R = 2^32), 64: 2^31 <= M < 2^58 (R = 2^62)
+  uint32_t run;        // indices per lane per chunk; a chunk is 256 * run indices
 };
 
 // Segments of a single query, passed by value as a kernel argument.
@@ -39,10 +39,10 @@ struct FinQuery {
   uint32_t want_status, status_idx;
 };
 
-hipError_t launch_head_args(int Lk, const HeadSegTable &tab, uint64_t nchunks, uint32_t run,
-                            int grid, unsigned long long *acc, hipStream_t st);
-hipError_t launch_head_ptr(int Lk, const HeadSeg *segs, int nseg, uint64_t nchunks, uint32_t run,
-                           int grid, unsigned long long *acc, hipStream_t st);
+hipError_t launch_head_args(int Lk, const HeadSegTable &tab, uint64_t nchunks, int grid,
+                            unsigned long long *acc, hipStream_t st);
+hipError_t launch_head_ptr(int Lk, const HeadSeg *segs, int nseg, uint64_t nchunks, int grid,
+                           unsigned long long *acc, hipStream_t st);
 hipError_t launch_finalize(int Lk, const FinQuery &single, const FinQuery *qs, int nq,
                            const unsigned long long *acc, uint64_t *out, pi_status *status,
                            hipStream_t st);
