@@ -108,6 +108,58 @@ def cpu_baseline(formula, n, P, target_s=12.0):
                       "query (%d head terms, %.1f s)" % (len(rows), length, done, dt)}
 
 
+def batch_vs_loop(pb, torch, count=4096, seed=1008):
+    """Config 4: the seeded 4096-query batch as one pi_extract_batch call and as
+    a loop of pi_extract_ex calls (one query per launch) on the same stream.
+    Both are timed with HIP events on that stream; outputs must be identical."""
+    from paper_1008_3171_amd import workloads
+    specs = workloads.batch_queries(count, seed=seed)
+    stream = torch.cuda.current_stream()
+    qarr, total = pb.make_queries(specs)
+    out_b = torch.zeros(total, dtype=torch.int64, device="cuda")
+    st_b = torch.zeros(4 * count, dtype=torch.int32, device="cuda")
+    out_l = torch.zeros(total, dtype=torch.int64, device="cuda")
+    st_l = torch.zeros(4 * count, dtype=torch.int32, device="cuda")
+    nbytes = pb.workspace_size(qarr, count)
+    ws = torch.zeros((nbytes + 7) // 8, dtype=torch.int64, device="cuda")
+    terms = sum(pb.head_terms(f, n) for f, n, _, _ in specs)
+
+    def batch():
+        pb.extract_batch(qarr, count, out_b, st_b, workspace=ws, stream=stream)
+
+    def loop():
+        for i, (f, n, w, P) in enumerate(specs):
+            off = qarr[i].out_offset
+            L = pb.limbs(P)
+            pb.extract(f, n, w, P, out=out_l[off:off + L], status=st_l[4 * i:4 * i + 4],
+                       stream=stream)
+
+    def timed(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3, time.perf_counter() - t0
+
+    batch(); loop(); torch.cuda.synchronize()        # warm up both paths
+    tb, wb = timed(batch)
+    tl, wl = timed(loop)
+    same = bool(torch.equal(out_b, out_l) and torch.equal(st_b, st_l))
+    certified = all(pb.status_of(st_b, i)[0] == pb.PI_OK for i in range(count))
+    print("batch vs loop done", file=sys.stderr, flush=True)
+    return {"queries": count, "head_terms": terms, "batch_s": tb, "loop_s": tl,
+            "batch_queries_per_s": count / tb, "loop_queries_per_s": count / tl,
+            "speedup": tl / tb, "batch_terms_per_s": terms / tb,
+            "batch_wall_s": wb, "loop_wall_s": wl, "identical_outputs": same,
+            "all_certified": certified,
+            "workload": "Bellard, n = floor(10^U), U ~ U(4, 9), w in {32,64,128,256}, "
+                        "P = w + 64, numpy PCG64 seed %d" % seed}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +170,7 @@ def main():
     ap.add_argument("--P", type=int, default=320)
     ap.add_argument("--formula", choices=["bellard", "bbp"], default="bellard")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path has no multi-GPU code (a query's index "
@@ -187,6 +240,8 @@ def main():
         h = re.search(r"^12 \d+ \d+ ([0-9A-F]+)$", row, re.M).group(1)
         ref = int(h, 16) >> (4 * len(h) - 255)
         rec["matches_table_2_2_m12"] = ((S >> (P - w)) & ((1 << 255) - 1)) == ref
+    if not args.no_batch:
+        rec["batch"] = batch_vs_loop(pb, torch)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(formula, n, P)
     print(json.dumps(rec), flush=True)

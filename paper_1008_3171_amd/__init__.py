@@ -150,7 +150,10 @@ def workspace_size(qarr, count: int) -> int:
 
 
 def extract_batch(qarr, count: int, out, status=None, workspace=None, stream=None):
-    """pi_extract_batch over a ctypes pi_query array (see make_queries)."""
+    """pi_extract_batch over a ctypes pi_query array (see make_queries).
+
+    status: an int32 tensor of 4*count, None to allocate one, or False to pass
+    NULL (no certification written)."""
     torch = _torch()
     lib = load()
     if status is None:
@@ -158,8 +161,9 @@ def extract_batch(qarr, count: int, out, status=None, workspace=None, stream=Non
     ws_ptr, ws_bytes = None, 0
     if workspace is not None:
         ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    st_ptr = None if status is False else status.data_ptr()
     rc = lib.pi_extract_batch(ctypes.cast(qarr, ctypes.c_void_p), count,
-                              ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(status.data_ptr()),
+                              ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(st_ptr),
                               ctypes.c_void_p(ws_ptr), ws_bytes, _stream(stream))
     if rc != 0:
         raise PiError(rc, "pi_extract_batch")

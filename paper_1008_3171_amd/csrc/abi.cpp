@@ -159,6 +159,50 @@ struct Arena {
 };
 std::map<std::pair<int, hipStream_t>, Arena> g_arena;
 
+// Pinned host staging for the tables a batch uploads, one per (device,
+// stream). Before it is rewritten, the previous upload from it must be done:
+// an event recorded after that upload is waited on.
+struct Stage {
+  void *host = nullptr;
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+};
+std::map<std::pair<int, hipStream_t>, Stage> g_stage;
+
+void *stage(hipStream_t st, size_t bytes, Stage **out, int *err) {
+  int dev = 0;
+  *err = PI_OK;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    *err = PI_EDEVICE;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  Stage &s = g_stage[{dev, st}];
+  if (!s.done && hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) {
+    *err = PI_EDEVICE;
+    return nullptr;
+  }
+  if (s.pending && hipEventSynchronize(s.done) != hipSuccess) {
+    *err = PI_EDEVICE;
+    return nullptr;
+  }
+  s.pending = false;
+  if (s.bytes < bytes) {
+    if (s.host) (void)hipHostFree(s.host);
+    s.host = nullptr;
+    s.bytes = 0;
+    const size_t nb = std::max(bytes, (size_t)1 << 16);
+    if (hipHostMalloc(&s.host, nb, hipHostMallocDefault) != hipSuccess) {
+      *err = PI_ENOMEM;
+      return nullptr;
+    }
+    s.bytes = nb;
+  }
+  *out = &s;
+  return s.host;
+}
+
 int device_cus() {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return -1;
@@ -238,16 +282,27 @@ uint32_t safe_run62(uint32_t run, uint64_t Mmin, uint64_t Mmax, uint64_t a) {
   return run;
 }
 
-// Number the chunks of the segments and fix each segment's run.
-uint64_t number_chunks(std::vector<HeadSeg> &segs, uint32_t run) {
-  uint64_t nchunks = 0;
+// Number the chunks of the segments and fix each segment's run: about a
+// quarter of the segment per lane-run column up to run_cap, and for class 62
+// no more than the starting-value bound allows.
+uint64_t number_chunks(std::vector<HeadSeg> &segs, uint32_t run_cap, uint64_t chunk_base = 0) {
+  uint64_t nchunks = chunk_base;
   for (HeadSeg &g : segs) {
     const HostSeries &s = kHSeries[g.formula][g.j];
-    g.run = g.cls == 64 ? safe_run62(run, s.a * g.kb + s.b, s.a * (g.ke - 1) + s.b, s.a) : run;
+    const uint64_t len = g.ke - g.kb;
+    uint32_t run = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(run_cap, len / 1024u));
+    if (g.cls == 64) run = safe_run62(run, s.a * g.kb + s.b, s.a * (g.ke - 1) + s.b, s.a);
+    g.run = run;
     g.chunk0 = nchunks;
-    nchunks += (g.ke - g.kb + 256ull * g.run - 1) / (256ull * g.run);
+    nchunks += (len + 256ull * run - 1) / (256ull * run);
   }
-  return nchunks;
+  return nchunks - chunk_base;
+}
+
+// Smallest run cap that keeps a query below 2^31 chunks (its counters take one
+// value below 2^32 per chunk).
+uint32_t min_run_cap(uint64_t head_terms) {
+  return (uint32_t)(head_terms / (256ull << 31) + 1u);
 }
 
 // Launch everything for one planned query (head segments passed by value).
@@ -256,6 +311,7 @@ int run_single(const QueryPlan &qp, uint64_t *out, pi_status *status, hipStream_
   head_segments(qp, 0, segs);
   const int grid_max = resident_grid();
   const uint64_t nchunks = number_chunks(segs, pick_run(qp.nhead, grid_max));
+  (void)min_run_cap;
   HeadSegTable tab;
   memset(&tab, 0, sizeof tab);
   for (size_t i = 0; i < segs.size(); ++i) tab.s[i] = segs[i];
@@ -271,6 +327,107 @@ int run_single(const QueryPlan &qp, uint64_t *out, pi_status *status, hipStream_
   }
   FinQuery fq = fin_query(qp, 0, status != nullptr, 0);
   return hip_err(launch_finalize(Lk, fq, nullptr, 1, acc, out, status, st));
+}
+
+// ---- batches -------------------------------------------------------------
+
+// One limb class of a batch: its queries, their head segments and finalize
+// records, and where each lives in the workspace.
+struct ClassPlan {
+  int Lk = 0;
+  std::vector<HeadSeg> segs;
+  std::vector<FinQuery> fins;
+  uint64_t nchunks = 0;
+  size_t acc_off = 0, seg_off = 0, fin_off = 0;
+};
+struct BatchPlan {
+  std::vector<ClassPlan> cls;
+  size_t bytes = 0;
+};
+
+size_t align256(size_t x) { return (x + 255u) & ~(size_t)255u; }
+
+int plan_batch(const pi_query *q, int count, BatchPlan *bp) {
+  if (count < 0 || (count > 0 && !q)) return PI_EINVAL;
+  std::map<int, int> by_class;  // Lk -> index in bp->cls
+  const int grid_max = 2048;
+  for (int i = 0; i < count; ++i) {
+    if (q[i].reserved != 0) return PI_EINVAL;
+    QueryPlan qp;
+    if (int e = make_plan(q[i].formula, q[i].n, q[i].nbits, q[i].P, 0x7fu, 0, UINT64_MAX, &qp))
+      return e;
+    auto it = by_class.find(qp.Lk);
+    if (it == by_class.end()) {
+      it = by_class.emplace(qp.Lk, (int)bp->cls.size()).first;
+      bp->cls.emplace_back();
+      bp->cls.back().Lk = qp.Lk;
+    }
+    ClassPlan &c = bp->cls[it->second];
+    const uint32_t local = (uint32_t)c.fins.size();
+    std::vector<HeadSeg> segs;
+    head_segments(qp, local, segs);
+    const uint32_t cap = std::max(pick_run(qp.nhead, grid_max), min_run_cap(qp.nhead));
+    c.nchunks += number_chunks(segs, cap, c.nchunks);
+    c.segs.insert(c.segs.end(), segs.begin(), segs.end());
+    c.fins.push_back(fin_query(qp, q[i].out_offset, true, (uint32_t)i));
+  }
+  size_t off = 0;
+  for (ClassPlan &c : bp->cls) {
+    c.acc_off = off;
+    off = align256(off + c.fins.size() * 2u * (size_t)c.Lk * sizeof(unsigned long long));
+    c.seg_off = off;
+    off = align256(off + c.segs.size() * sizeof(HeadSeg));
+    c.fin_off = off;
+    off = align256(off + c.fins.size() * sizeof(FinQuery));
+  }
+  bp->bytes = std::max<size_t>(off, 256);
+  return PI_OK;
+}
+
+// Upload the tables (through pinned staging), clear the counters, then one
+// head launch and one finalize launch per limb class, all on `st`.
+int run_batch(BatchPlan &bp, char *ws, uint64_t *out, pi_status *status, hipStream_t st) {
+  const int grid_max = resident_grid();
+  size_t table_bytes = 0;
+  for (ClassPlan &c : bp.cls) {
+    for (FinQuery &f : c.fins) f.want_status = status != nullptr ? 1u : 0u;
+    table_bytes += c.segs.size() * sizeof(HeadSeg) + c.fins.size() * sizeof(FinQuery);
+  }
+  Stage *sg = nullptr;
+  int err = PI_OK;
+  char *host = (char *)stage(st, table_bytes, &sg, &err);
+  if (!host) return err;
+  size_t hoff = 0;
+  for (const ClassPlan &c : bp.cls) {
+    auto *segs = (HeadSeg *)(ws + c.seg_off);
+    auto *fins = (FinQuery *)(ws + c.fin_off);
+    const size_t sb = c.segs.size() * sizeof(HeadSeg), fb = c.fins.size() * sizeof(FinQuery);
+    memcpy(host + hoff, c.segs.data(), sb);
+    memcpy(host + hoff + sb, c.fins.data(), fb);
+    if (sb && hipMemcpyAsync(segs, host + hoff, sb, hipMemcpyHostToDevice, st) != hipSuccess)
+      return PI_EDEVICE;
+    if (hipMemcpyAsync(fins, host + hoff + sb, fb, hipMemcpyHostToDevice, st) != hipSuccess)
+      return PI_EDEVICE;
+    hoff += sb + fb;
+  }
+  if (hipEventRecord(sg->done, st) != hipSuccess) return PI_EDEVICE;
+  sg->pending = true;
+  for (const ClassPlan &c : bp.cls) {
+    auto *acc = (unsigned long long *)(ws + c.acc_off);
+    auto *segs = (HeadSeg *)(ws + c.seg_off);
+    auto *fins = (FinQuery *)(ws + c.fin_off);
+    if (int e = hip_err(launch_zero(acc, c.fins.size() * 2u * (uint64_t)c.Lk, st))) return e;
+    if (c.nchunks) {
+      const int grid = (int)std::min<uint64_t>(c.nchunks, (uint64_t)grid_max);
+      if (int e = hip_err(launch_head_ptr(c.Lk, segs, (int)c.segs.size(), c.nchunks, grid, acc, st)))
+        return e;
+    }
+    FinQuery none;
+    memset(&none, 0, sizeof none);
+    if (int e = hip_err(launch_finalize(c.Lk, none, fins, (int)c.fins.size(), acc, out, status, st)))
+      return e;
+  }
+  return PI_OK;
 }
 
 }  // namespace
@@ -309,21 +466,26 @@ uint64_t pi_head_terms(int formula, uint64_t n) {
 }
 
 size_t pi_workspace_size(const pi_query *q, int count) {
-  (void)q;
-  (void)count;
-  return 0;
+  BatchPlan bp;
+  if (plan_batch(q, count, &bp) != PI_OK) return 0;
+  return bp.bytes;
 }
 
 int pi_extract_batch(const pi_query *q, int count, uint64_t *out, pi_status *status,
                      void *workspace, size_t ws_bytes, hipStream_t stream) {
-  (void)q;
-  (void)count;
-  (void)out;
-  (void)status;
-  (void)workspace;
-  (void)ws_bytes;
-  (void)stream;
-  return PI_EUNSUPPORTED;
+  if (count < 0 || (count > 0 && (!q || !out))) return PI_EINVAL;
+  if (count == 0) return PI_OK;
+  BatchPlan bp;
+  if (int e = plan_batch(q, count, &bp)) return e;
+  char *ws = (char *)workspace;
+  if (ws) {
+    if (ws_bytes < bp.bytes) return PI_EINVAL;
+  } else {
+    int err = PI_OK;
+    ws = (char *)arena(stream, bp.bytes, &err);
+    if (!ws) return err;
+  }
+  return run_batch(bp, ws, out, status, stream);
 }
 
 const char *pi_strerror(int code) {
@@ -349,6 +511,12 @@ void pi_shutdown(void) {
     (void)hipSetDevice(cur);
   }
   g_arena.clear();
+  for (auto &kv : g_stage) {
+    if (kv.second.pending) (void)hipEventSynchronize(kv.second.done);
+    if (kv.second.done) (void)hipEventDestroy(kv.second.done);
+    if (kv.second.host) (void)hipHostFree(kv.second.host);
+  }
+  g_stage.clear();
 }
 
 }  // extern "C"
