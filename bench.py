@@ -160,6 +160,55 @@ def batch_vs_loop(pb, torch, count=4096, seed=1008):
                         "P = w + 64, numpy PCG64 seed %d" % seed}
 
 
+def serving_bench(pb, torch, count=1000, seed=3171, hi_exp=10.0, rho=0.8):
+    """Config 5, scaled: `count` queries of the seeded serving stream
+    (n = floor(10^U), U ~ U(3, hi_exp), BBP or Bellard 50/50, w in {64, 256},
+    P = w + 64). First every query arrives at once, which measures capacity
+    (queries/s); then the same queries arrive as a Poisson stream at rho times
+    that capacity, and latency = completion - arrival is recorded."""
+    from paper_1008_3171_amd import serving, workloads
+    base = workloads.serving_stream(count, seed=seed, hi_exp=hi_exp, rate=1.0)
+    burst = [(0.0,) + q[1:] for q in base]
+    srv = pb.Server(max_active=1024, step_terms=1 << 30)
+    res0, lat0, mk0, st0 = serving.run_stream(srv, burst)
+    capacity = count / mk0
+    lam = rho * capacity
+    res1, lat1, mk1, st1 = serving.run_stream(srv, base, time_scale=1.0 / lam)
+    srv.close()
+    terms = sum(pb.head_terms(f, n) for _, f, n, _, _ in base)
+    print("serving done", file=sys.stderr, flush=True)
+    return {"queries": count, "head_terms": terms, "capacity_qps": capacity,
+            "burst_makespan_s": mk0, "rate_qps": lam, "rho": rho,
+            "makespan_s": mk1, "qps": count / mk1, "terms_per_s": terms / mk1,
+            "p50_latency_s": serving.percentile(lat1, 50),
+            "p99_latency_s": serving.percentile(lat1, 99),
+            "steps": st1, "identical_to_burst": res0 == res1,
+            "all_certified": all(v[1] == pb.PI_OK for v in res1.values()),
+            "workload": "n = floor(10^U), U ~ U(3, %g), BBP/Bellard 1/2 each, w in {64, 256}, "
+                        "P = w + 64, numpy PCG64 seed %d, Poisson arrivals" % (hi_exp, seed)}
+
+
+def paper_slice(pb, torch):
+    """The paper-scale slice: Bellard at n = 2*10^15, k in [10^14, 10^14 + 2^32)
+    for all seven series (moduli near 2^50), as seven pi_sum_slice calls."""
+    stream = torch.cuda.current_stream()
+    n, P = 2 * 10 ** 15, 320
+    k0, k1 = 10 ** 14, 10 ** 14 + 2 ** 32
+    outs = [torch.zeros(pb.limbs(P), dtype=torch.int64, device="cuda") for _ in range(7)]
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    for rep in range(2):                       # the first pass warms up
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for j in range(7):
+            pb.sum_slice(pb.term_id(pb.BELLARD, j), n, k0, k1, P, out=outs[j], stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3
+    return {"n": n, "k0": k0, "k1": k1, "terms": 7 * (k1 - k0), "seconds": s,
+            "terms_per_s": 7 * (k1 - k0) / s}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +220,7 @@ def main():
     ap.add_argument("--formula", choices=["bellard", "bbp"], default="bellard")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path has no multi-GPU code (a query's index "
@@ -242,6 +292,9 @@ def main():
         rec["matches_table_2_2_m12"] = ((S >> (P - w)) & ((1 << 255) - 1)) == ref
     if not args.no_batch:
         rec["batch"] = batch_vs_loop(pb, torch)
+        rec["paper_slice"] = paper_slice(pb, torch)
+    if not args.no_serving:
+        rec["serving"] = serving_bench(pb, torch)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(formula, n, P)
     print(json.dumps(rec), flush=True)

@@ -41,6 +41,12 @@
 extern "C" {
 #endif
 
+#if defined(__GNUC__)
+#define PI_API __attribute__((visibility("default")))
+#else
+#define PI_API
+#endif
+
 /* Formulas: eq (1.1) (as written in eq (3.1)) and eq (1.2). */
 enum { PI_BBP = 0, PI_BELLARD = 1 };
 
@@ -77,14 +83,14 @@ typedef struct {
  * precision than you report").
  *   out: device uint64[ceil((nbits+64)/64)], the left-aligned P-bit sum S.
  * Returns PI_OK or an error; certification is reported by pi_extract_ex. */
-int pi_extract(int formula, uint64_t n, uint32_t nbits, uint64_t *out, hipStream_t stream);
+PI_API int pi_extract(int formula, uint64_t n, uint32_t nbits, uint64_t *out, hipStream_t stream);
 
 /* As pi_extract with an explicit precision P >= nbits (e.g. P = 96 for 64
  * result bits) and an optional device pi_status (may be NULL).
  * The tail of each series is summed up to its stop index: the first E < 0
  * index whose P-bit truncation is 0 (every later term is smaller).
  *   out: device uint64[ceil(P/64)]. status: device pi_status or NULL. */
-int pi_extract_ex(int formula, uint64_t n, uint32_t nbits, uint32_t P, uint64_t *out,
+PI_API int pi_extract_ex(int formula, uint64_t n, uint32_t nbits, uint32_t P, uint64_t *out,
                   pi_status *status, hipStream_t stream);
 
 /* One summand of eq (3.1), restricted to an index range, as in the
@@ -93,7 +99,7 @@ int pi_extract_ex(int formula, uint64_t n, uint32_t nbits, uint32_t P, uint64_t 
  * and tail indices may both be in the range; tail terms past the stop index
  * are zero. Sums over disjoint ranges add up (mod 2^P) to the full sum.
  *   out: device uint64[ceil(P/64)], left-aligned. */
-int pi_sum_slice(int term, uint64_t n, uint64_t k0, uint64_t k1, uint32_t P, uint64_t *out,
+PI_API int pi_sum_slice(int term, uint64_t n, uint64_t k0, uint64_t k1, uint32_t P, uint64_t *out,
                  hipStream_t stream);
 
 /* A query of a batch. out_offset is in uint64 limbs from the batch's `out`;
@@ -115,21 +121,73 @@ typedef struct {
  *   status: device pi_status[count] or NULL.
  *   workspace: device memory of at least pi_workspace_size(q, count) bytes,
  *   or NULL to use the library's per-stream scratch. */
-int pi_extract_batch(const pi_query *q, int count, uint64_t *out, pi_status *status,
+PI_API int pi_extract_batch(const pi_query *q, int count, uint64_t *out, pi_status *status,
                      void *workspace, size_t ws_bytes, hipStream_t stream);
 
 /* Bytes of device workspace pi_extract_batch needs for these queries. */
-size_t pi_workspace_size(const pi_query *q, int count);
+PI_API size_t pi_workspace_size(const pi_query *q, int count);
 
 /* Number of head terms (E >= 0 indices) of an extraction: sum over series of
  * floor((n-1+c_j)/step)+1 where that is positive. Host-only arithmetic. */
-uint64_t pi_head_terms(int formula, uint64_t n);
+PI_API uint64_t pi_head_terms(int formula, uint64_t n);
 
 /* Static text for a return code. */
-const char *pi_strerror(int code);
+PI_API const char *pi_strerror(int code);
 
 /* Release the library's scratch memory on every device. */
-void pi_shutdown(void);
+PI_API void pi_shutdown(void);
+
+/* ---- serving: continuous batching ------------------------------------------
+ *
+ * A server owns a stream-ordered pool of query slots on one device. Queries
+ * are admitted while a slot is free (the pool is sized at creation from the
+ * device's free memory), each step gives every active query a fair share of
+ * the step's head terms, and a query's carry-save partial sum stays in its
+ * device slot across steps until its last chunk is done; it is then
+ * finalized and its result can be polled. A query's result is bit-identical
+ * to pi_extract_ex on its own, whatever else is in flight. This is the
+ * one-GPU counterpart of section 4.3's admission of small jobs as cluster
+ * slots free up. A server is not thread-safe; use one per host thread. */
+typedef struct pi_server pi_server;
+
+/* A finished query, copied to the host by pi_server_poll. */
+typedef struct {
+  uint64_t tag;        /* the caller's tag from pi_server_submit */
+  int32_t code;        /* PI_OK when certified, PI_UNCERTAIN otherwise */
+  uint32_t P;
+  uint64_t nterms;     /* N, as in pi_status */
+  uint64_t limbs[17];  /* left-aligned S in the first ceil(P/64) limbs */
+} pi_result;
+
+/* PI_BUSY: pi_server_submit found no free slot; submit again after a step. */
+#define PI_BUSY 2
+
+/* Create a server on the current device and `stream`.
+ *   max_active: slots requested (reduced so the pool uses at most a quarter of
+ *   the device's free memory); step_terms: head terms per step (the step's
+ *   budget, shared fairly by the active queries). */
+PI_API int pi_server_create(uint32_t max_active, uint64_t step_terms, hipStream_t stream,
+                            pi_server **out);
+
+/* Admit one query (host struct; out_offset is ignored). Returns PI_OK,
+ * PI_BUSY when every slot is taken, or an argument error. */
+PI_API int pi_server_submit(pi_server *s, const pi_query *q, uint64_t tag);
+
+/* Run one step on the server's stream and wait for it; *finished (may be
+ * NULL) receives the number of queries that completed in it. */
+PI_API int pi_server_step(pi_server *s, uint32_t *finished);
+
+/* Move up to `max` completed results to `out` (host); *count receives how
+ * many. */
+PI_API int pi_server_poll(pi_server *s, pi_result *out, uint32_t max, uint32_t *count);
+
+/* Queries admitted and not yet finished. */
+PI_API uint32_t pi_server_active(const pi_server *s);
+
+/* Slots the server was created with (after the memory cap). */
+PI_API uint32_t pi_server_capacity(const pi_server *s);
+
+PI_API void pi_server_destroy(pi_server *s);
 
 #ifdef __cplusplus
 }

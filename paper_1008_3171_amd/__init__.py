@@ -185,3 +185,94 @@ def status_of(status_tensor, i: int = 0):
     """(code, nterms) of the i-th pi_status in an int32 tensor."""
     s = [int(v) & 0xFFFFFFFF for v in status_tensor[4 * i:4 * i + 4].cpu().tolist()]
     return s[0] if s[0] < 2 ** 31 else s[0] - 2 ** 32, s[2] | (s[3] << 32)
+
+
+class pi_result(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("code", ctypes.c_int32), ("P", ctypes.c_uint32),
+                ("nterms", ctypes.c_uint64), ("limbs", ctypes.c_uint64 * 17)]
+
+
+PI_BUSY = 2
+
+
+class Server:
+    """pi_server_*: continuous batching on one device and stream."""
+
+    def __init__(self, max_active: int = 1024, step_terms: int = 1 << 30, stream=None):
+        torch = _torch()
+        lib = load()
+        vp = ctypes.c_void_p
+        lib.pi_server_create.argtypes = [ctypes.c_uint32, ctypes.c_uint64, vp, ctypes.POINTER(vp)]
+        lib.pi_server_submit.argtypes = [vp, vp, ctypes.c_uint64]
+        lib.pi_server_step.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]
+        lib.pi_server_poll.argtypes = [vp, vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]
+        lib.pi_server_active.argtypes = [vp]
+        lib.pi_server_active.restype = ctypes.c_uint32
+        lib.pi_server_capacity.argtypes = [vp]
+        lib.pi_server_capacity.restype = ctypes.c_uint32
+        lib.pi_server_destroy.argtypes = [vp]
+        for f in (lib.pi_server_create, lib.pi_server_submit, lib.pi_server_step,
+                  lib.pi_server_poll):
+            f.restype = ctypes.c_int
+        self._lib = lib
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        rc = lib.pi_server_create(max_active, step_terms, ctypes.c_void_p(self._stream.cuda_stream),
+                                  ctypes.byref(h))
+        if rc != 0:
+            raise PiError(rc, "pi_server_create")
+        self._h = h
+        self._q = pi_query()
+        self._buf = (pi_result * 4096)()
+
+    def submit(self, formula: int, n: int, nbits: int, P: int, tag: int) -> bool:
+        """Admit a query; False when every slot is busy."""
+        q = self._q
+        q.formula, q.n, q.nbits, q.P, q.reserved, q.out_offset = formula, n, nbits, P, 0, 0
+        rc = self._lib.pi_server_submit(self._h, ctypes.byref(q), tag)
+        if rc == PI_BUSY:
+            return False
+        if rc != 0:
+            raise PiError(rc, "pi_server_submit")
+        return True
+
+    def step(self) -> int:
+        fin = ctypes.c_uint32()
+        rc = self._lib.pi_server_step(self._h, ctypes.byref(fin))
+        if rc != 0:
+            raise PiError(rc, "pi_server_step")
+        return fin.value
+
+    def poll(self):
+        """[(tag, S, code, nterms)] of the queries finished since the last poll."""
+        out = []
+        while True:
+            cnt = ctypes.c_uint32()
+            rc = self._lib.pi_server_poll(self._h, self._buf, len(self._buf), ctypes.byref(cnt))
+            if rc != 0:
+                raise PiError(rc, "pi_server_poll")
+            for r in self._buf[:cnt.value]:
+                L = limbs(r.P)
+                S = 0
+                for i in range(L):
+                    S |= int(r.limbs[i]) << (64 * i)
+                out.append((int(r.tag), S >> (64 * L - r.P), int(r.code), int(r.nterms)))
+            if cnt.value < len(self._buf):
+                return out
+
+    def active(self) -> int:
+        return int(self._lib.pi_server_active(self._h))
+
+    def capacity(self) -> int:
+        return int(self._lib.pi_server_capacity(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.pi_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -14,7 +14,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpibbp.so")
-SOURCES = ["kernels.hip", "abi.cpp"]
+SOURCES = ["kernels.hip", "abi.cpp", "server.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -22,6 +22,7 @@ HIPCC_FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-shared",
+    "-fvisibility=hidden",
     # packed fp32 instructions stay off (none are wanted in integer code)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",

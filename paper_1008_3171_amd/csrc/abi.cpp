@@ -16,12 +16,12 @@
 #include <utility>
 #include <vector>
 
+#include "host.h"
 #include "pibbp.h"
 #include "plan.h"
 
-using namespace pibbp;
-
-namespace {
+namespace pibbp {
+namespace host {
 
 struct HostSeries {
   int neg, c;
@@ -60,16 +60,6 @@ uint64_t first_zero(const HostSeries &s, int step, uint64_t d, uint32_t P) {
   return v < 0 ? 0 : (uint64_t)(v / step) + 1u;
 }
 
-struct QueryPlan {
-  int formula;
-  uint64_t d;
-  uint32_t P, w, Lq;
-  int Lk;
-  uint64_t hk0[7], hk1[7];  // head ranges
-  uint64_t tk0[7], tk1[7];  // tail ranges
-  uint64_t nhead;
-};
-
 // Fill a plan for series set `jmask` of `formula` over index range [k0, k1).
 int make_plan(int formula, uint64_t n, uint32_t w, uint32_t P, uint32_t jmask, uint64_t k0,
               uint64_t k1, QueryPlan *qp) {
@@ -101,7 +91,7 @@ int make_plan(int formula, uint64_t n, uint32_t w, uint32_t P, uint32_t jmask, u
 }
 
 // Head segments of a plan, split at the class-32/class-64 modulus boundary.
-void head_segments(const QueryPlan &qp, uint32_t query, std::vector<HeadSeg> &out) {
+void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &out) {
   for (int j = 0; j < kHJ[qp.formula]; ++j) {
     const HostSeries &s = kHSeries[qp.formula][j];
     const uint64_t kb = qp.hk0[j], ke = qp.hk1[j];
@@ -114,7 +104,7 @@ void head_segments(const QueryPlan &qp, uint32_t query, std::vector<HeadSeg> &ou
     g.formula = (uint32_t)qp.formula;
     g.j = (uint32_t)j;
     g.P = qp.P;
-    g.query = query;
+    g.acc_off = acc_off;
     if (kb < cut) {
       g.kb = kb;
       g.ke = cut;
@@ -130,7 +120,8 @@ void head_segments(const QueryPlan &qp, uint32_t query, std::vector<HeadSeg> &ou
   }
 }
 
-FinQuery fin_query(const QueryPlan &qp, uint64_t out_off, bool want_status, uint32_t sidx) {
+FinQuery fin_query(const QueryPlan &qp, uint64_t out_off, bool want_status, uint32_t sidx,
+                   uint32_t acc_off) {
   FinQuery f;
   memset(&f, 0, sizeof f);
   f.d = qp.d;
@@ -146,6 +137,7 @@ FinQuery fin_query(const QueryPlan &qp, uint64_t out_off, bool want_status, uint
   f.Lq = qp.Lq;
   f.want_status = want_status ? 1u : 0u;
   f.status_idx = sidx;
+  f.acc_off = acc_off;
   return f;
 }
 
@@ -285,7 +277,7 @@ uint32_t safe_run62(uint32_t run, uint64_t Mmin, uint64_t Mmax, uint64_t a) {
 // Number the chunks of the segments and fix each segment's run: about a
 // quarter of the segment per lane-run column up to run_cap, and for class 62
 // no more than the starting-value bound allows.
-uint64_t number_chunks(std::vector<HeadSeg> &segs, uint32_t run_cap, uint64_t chunk_base = 0) {
+uint64_t number_chunks(std::vector<HeadSeg> &segs, uint32_t run_cap, uint64_t chunk_base) {
   uint64_t nchunks = chunk_base;
   for (HeadSeg &g : segs) {
     const HostSeries &s = kHSeries[g.formula][g.j];
@@ -310,8 +302,7 @@ int run_single(const QueryPlan &qp, uint64_t *out, pi_status *status, hipStream_
   std::vector<HeadSeg> segs;
   head_segments(qp, 0, segs);
   const int grid_max = resident_grid();
-  const uint64_t nchunks = number_chunks(segs, pick_run(qp.nhead, grid_max));
-  (void)min_run_cap;
+  const uint64_t nchunks = number_chunks(segs, pick_run(qp.nhead, grid_max), 0);
   HeadSegTable tab;
   memset(&tab, 0, sizeof tab);
   for (size_t i = 0; i < segs.size(); ++i) tab.s[i] = segs[i];
@@ -325,7 +316,7 @@ int run_single(const QueryPlan &qp, uint64_t *out, pi_status *status, hipStream_
     const int grid = (int)std::min<uint64_t>(nchunks, (uint64_t)grid_max);
     if (int e = hip_err(launch_head_args(Lk, tab, nchunks, grid, acc, st))) return e;
   }
-  FinQuery fq = fin_query(qp, 0, status != nullptr, 0);
+  FinQuery fq = fin_query(qp, 0, status != nullptr, 0, 0);
   return hip_err(launch_finalize(Lk, fq, nullptr, 1, acc, out, status, st));
 }
 
@@ -365,11 +356,11 @@ int plan_batch(const pi_query *q, int count, BatchPlan *bp) {
     ClassPlan &c = bp->cls[it->second];
     const uint32_t local = (uint32_t)c.fins.size();
     std::vector<HeadSeg> segs;
-    head_segments(qp, local, segs);
+    head_segments(qp, local * 2u * (uint32_t)qp.Lk, segs);
     const uint32_t cap = std::max(pick_run(qp.nhead, grid_max), min_run_cap(qp.nhead));
     c.nchunks += number_chunks(segs, cap, c.nchunks);
     c.segs.insert(c.segs.end(), segs.begin(), segs.end());
-    c.fins.push_back(fin_query(qp, q[i].out_offset, true, (uint32_t)i));
+    c.fins.push_back(fin_query(qp, q[i].out_offset, true, (uint32_t)i, local * 2u * (uint32_t)qp.Lk));
   }
   size_t off = 0;
   for (ClassPlan &c : bp->cls) {
@@ -430,7 +421,11 @@ int run_batch(BatchPlan &bp, char *ws, uint64_t *out, pi_status *status, hipStre
   return PI_OK;
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace pibbp
+
+using namespace pibbp;
+using namespace pibbp::host;
 
 extern "C" {
 

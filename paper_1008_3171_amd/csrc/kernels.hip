@@ -224,7 +224,7 @@ __device__ void head_chunks(const HeadSeg *segs, int nseg, uint64_t nchunks,
     else
       lane_run32<L>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum);
     if (neg) neg_limbs<L>(sum);
-    wg_fold<L>(sum, red, sums, acc + (uint64_t)sg.query * 2u * L);
+    wg_fold<L>(sum, red, sums, acc + sg.acc_off);
   }
 }
 
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinQuery single, const Fi
     if (neg) neg_limbs<L>(t);
     add_limbs<L>(sum, t);
   }
-  if (tid < 2u * L) cnt[tid] = acc[(uint64_t)blockIdx.x * 2u * L + tid];
+  if (tid < 2u * L) cnt[tid] = acc[(uint64_t)q.acc_off + tid];
   __syncthreads();
   if (nz) atomicAdd(&nz_total, nz);
 #pragma unroll

@@ -16,7 +16,8 @@ struct HeadSeg {
   uint64_t kb, ke;
   uint64_t chunk0;
   uint64_t d;          // n - 1
-  uint32_t formula, j, P, query;
+  uint32_t formula, j, P;
+  uint32_t acc_off;    // the query's carry-save counters: acc + acc_off
   uint32_t cls;        // 32: M < 2^31 (R = 2^32), 64: 2^31 <= M < 2^58 (R = 2^62)
   uint32_t run;        // indices per lane per chunk; a chunk is 256 * run indices
 };
@@ -37,6 +38,8 @@ struct FinQuery {
   uint64_t tk0[7], tk1[7];
   uint32_t formula, P, w, Lq;
   uint32_t want_status, status_idx;
+  uint32_t acc_off;    // the query's counters: acc + acc_off
+  uint32_t pad;
 };
 
 hipError_t launch_head_args(int Lk, const HeadSegTable &tab, uint64_t nchunks, int grid,

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "pibbp.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(pi_[a-z_0-9]+)\s*\(",
+    return sorted(set(re.findall(r"^\s*PI_API\s+(?:const\s+)?[a-z_0-9]+\s*\*?\s*(pi_[a-z_0-9]+)\s*\(",
                                  src, flags=re.M)))
 
 
@@ -23,7 +23,7 @@ def test_library_exports_every_declared_symbol():
     lib = pb.load()
     names = declared_functions()
     assert {"pi_extract", "pi_extract_ex", "pi_sum_slice", "pi_extract_batch",
-            "pi_workspace_size", "pi_strerror"} <= set(names)
+            "pi_workspace_size", "pi_strerror", "pi_server_create", "pi_server_step"} <= set(names)
     for name in names:
         assert hasattr(lib, name), name
 

@@ -1,0 +1,95 @@
+"""The continuous-batching server: every query's result is bit-identical to
+pi_extract_ex alone, whatever else is in flight; slots are admitted and
+reused; a large query keeps its partial sum on the device across steps."""
+import random
+
+import pytest
+
+import oracle
+import paper_1008_3171_amd as pb
+from paper_1008_3171_amd import serving, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def alone(f, n, w, P):
+    out, st = pb.extract(f, n, w, P)
+    code, N = pb.status_of(st)
+    return pb.to_int(out, P), code, N
+
+
+def test_results_alone_equal_results_in_the_mix():
+    stream = workloads.serving_stream(400, seed=3171, hi_exp=8.0, rate=4000.0)
+    srv = pb.Server(max_active=48, step_terms=1 << 22)
+    results, lat, makespan, steps = serving.run_stream(srv, stream)
+    srv.close()
+    assert len(results) == len(stream)
+    assert steps > 10                       # the queries really overlapped
+    for tag, (ta, f, n, w, P) in enumerate(stream):
+        assert results[tag] == alone(f, n, w, P), (tag, f, n, w, P)
+    rng = random.Random(3171)
+    small = [t for t, q in enumerate(stream) if q[2] <= 2_000_000]
+    for tag in rng.sample(small, 25):
+        ta, f, n, w, P = stream[tag]
+        S, N, cert = oracle.extract(f, n, w, P, 8)
+        assert results[tag] == (S, 0 if cert else 1, N)
+
+
+def test_admission_busy_and_slot_reuse():
+    srv = pb.Server(max_active=2, step_terms=1 << 20)
+    assert srv.capacity() == 2
+    assert srv.submit(pb.BELLARD, 10 ** 6, 64, 128, 1)
+    assert srv.submit(pb.BBP, 12345, 256, 320, 2)
+    assert not srv.submit(pb.BELLARD, 999, 8, 72, 3)        # no free slot
+    got = {}
+    while srv.active():
+        srv.step()
+        for tag, S, code, N in srv.poll():
+            got[tag] = (S, code, N)
+    assert srv.submit(pb.BELLARD, 999, 8, 72, 3)            # a slot came back
+    while srv.active():
+        srv.step()
+        for tag, S, code, N in srv.poll():
+            got[tag] = (S, code, N)
+    srv.close()
+    assert got[1] == alone(pb.BELLARD, 10 ** 6, 64, 128)
+    assert got[2] == alone(pb.BBP, 12345, 256, 320)
+    assert got[3] == alone(pb.BELLARD, 999, 8, 72)
+    with pytest.raises(pb.PiError):
+        pb.Server(max_active=4).submit(pb.BELLARD, 0, 8, 72, 0)
+
+
+def test_large_query_spans_many_steps_while_small_ones_finish():
+    srv = pb.Server(max_active=16, step_terms=1 << 24)
+    big = (pb.BELLARD, 10 ** 9 + 1, 256, 320)
+    assert srv.submit(*big, 0)
+    steps = 0
+    got = {}
+    small = [(pb.BBP, 1000 + 7 * i, 64, 128) for i in range(40)]
+    for i, q in enumerate(small):
+        while not srv.submit(*q, i + 1):
+            srv.step()
+            steps += 1
+            got.update({t: (S, c, N) for t, S, c, N in srv.poll()})
+    while srv.active():
+        srv.step()
+        steps += 1
+        got.update({t: (S, c, N) for t, S, c, N in srv.poll()})
+    srv.close()
+    assert steps > 20
+    assert got[0] == alone(*big)
+    for i, q in enumerate(small):
+        assert got[i + 1] == alone(*q)
+
+
+def test_paper_scale_slice_subslices_match_oracle():
+    # n = 2*10^15, k in [10^14, 10^14 + 2^32): moduli near 2^50; seeded
+    # 10^6-term sub-slices of it, every series, against the oracle
+    n = 2 * 10 ** 15
+    rng = random.Random(1008)
+    for j in range(7):
+        k0 = 10 ** 14 + rng.randrange(0, 2 ** 32 - 150_000)
+        k1 = k0 + 142_858
+        P = 320
+        got = pb.to_int(pb.sum_slice(pb.term_id(pb.BELLARD, j), n, k0, k1, P), P)
+        assert got == oracle.sum_slice(oracle.BELLARD, j, n - 1, k0, k1, P, 8)[0], (j, k0)
