@@ -221,6 +221,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first copy this many MiB device-to-device twice (a plain copy "
+                         "kernel of known size, to calibrate memory counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path has no multi-GPU code (a query's index "
@@ -234,6 +237,13 @@ def main():
     formula = pb.BELLARD if args.formula == "bellard" else pb.BBP
     n, w, P = args.n, args.nbits, args.P
     stream = torch.cuda.current_stream()
+    if args.copy_probe_mib:
+        src = torch.ones(args.copy_probe_mib << 17, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     out = torch.zeros(pb.limbs(P), dtype=torch.int64, device="cuda")
     st = torch.zeros(4, dtype=torch.int32, device="cuda")
     for _ in range(args.warmup):

@@ -25,7 +25,7 @@
  *    caller; the library never frees them. Query tables are HOST pointers.
  *  - Calls are asynchronous on `stream`: argument validation is synchronous
  *    and returns an error code; results are ready when the stream is.
- *  - Limits: 1 <= P <= PI_MAX_P; every modulus a_j*k+b_j below 2^58 and
+ *  - Limits: 1 <= P <= PI_MAX_P; every modulus a_j*k+b_j below 2^54 and
  *    n + P below 2^62 (otherwise PI_EUNSUPPORTED).
  *  - Calls on one device share internal scratch per stream; calls on
  *    different streams may overlap, calls on one stream are serialized.

@@ -38,7 +38,7 @@ const int kHJ[2] = {4, 7};
 const int kLimbClasses[] = {1, 2, 3, 4, 5, 6, 8, 12, 17};
 
 constexpr uint64_t kClass32Limit = 1ull << 31;
-constexpr uint64_t kModulusLimit = 1ull << 58;
+constexpr uint64_t kModulusLimit = 1ull << 54;
 
 int limb_class(uint32_t P) {
   const int Lq = (int)((P + 63u) / 64u);
@@ -258,15 +258,16 @@ int hip_err(hipError_t e) { return e == hipSuccess ? PI_OK : PI_EDEVICE; }
 // Largest run (indices per lane per chunk) a class-62 segment with moduli in
 // [Mmin, Mmax] and modulus step a allows. A lane's ladder starts from
 // g = 2^62 - qM with q = floor(2^62/M_last), so g < (e+1)M with
-// e <= 2^62 2a run / M^2 + 1; the first squaring needs (e+1)^2 M < 2^62.
-// f(M) = (2^63 a run / M^2 + 2)^2 M is convex, so checking both ends of the
-// modulus range suffices; a factor 2 of margin covers rounding here.
+// e + 1 <= 2^63 a run / M^2 + 2. The first squaring needs g^2 < 2^62 M (its
+// output then stays below 8M) and g < 2^57 (digit bounds); with a margin of
+// 4 and 2 this asks (e+1)^2 M < 2^60 and (e+1) M < 2^56. Both bounds are
+// largest at an end of the modulus range.
 uint32_t safe_run62(uint32_t run, uint64_t Mmin, uint64_t Mmax, uint64_t a) {
   auto ok = [&](double r) {
     const double A = std::ldexp((double)a * r, 63);
     for (double M : {(double)Mmin, (double)Mmax}) {
-      const double e2 = A / (M * M) + 2.0;
-      if (e2 * e2 * M >= std::ldexp(1.0, 61)) return false;
+      const double e1 = A / (M * M) + 2.0;
+      if (e1 * e1 * M >= std::ldexp(1.0, 60) || e1 * M >= std::ldexp(1.0, 56)) return false;
     }
     return true;
   };
@@ -490,7 +491,7 @@ const char *pi_strerror(int code) {
     case PI_EINVAL: return "invalid argument";
     case PI_ENOMEM: return "out of device memory";
     case PI_EDEVICE: return "HIP runtime or device error";
-    case PI_EUNSUPPORTED: return "outside the supported range (modulus >= 2^58 or n too large)";
+    case PI_EUNSUPPORTED: return "outside the supported range (modulus >= 2^54 or n too large)";
     default: return "unknown error code";
   }
 }

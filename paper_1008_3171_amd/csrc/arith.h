@@ -17,7 +17,9 @@
 //
 // Two modulus classes keep the multiply count down:
 //  * class 32 (M < 2^31): R = 2^32, residues kept below M;
-//  * class 64 (2^31 <= M < 2^60): R = 2^64, residues kept below 2M.
+//  * class 62 (2^31 <= M < 2^54): R = 2^62, residues in two 31-bit digits,
+//    kept below 8M (the head kernel);
+//  * R = 2^64 with residues below 2M (M < 2^60): the few tail terms.
 // v_mad_u64_u32 issues at full rate on gfx950, so these are written in plain
 // 64-bit C and the compiler emits mad chains.
 #pragma once
@@ -79,35 +81,50 @@ __device__ __forceinline__ uint64_t mont_one64(uint64_t M) {
   return c;
 }
 
-// ---- class 62: R = 2^62, residues in two 31-bit digits, M < 2^58 ---------
+// ---- class 62: R = 2^62, residues in two 31-bit digits, M < 2^54 ---------
 //
-// x = d0 + d1 2^31 with d0 < 2^31. Every partial product is below 2^62 and
+// x = d0 + d1 2^31 with d0 < 2^31. Every partial product is below 2^63 and
 // every column sum below 2^64, so no carry ever has to be tracked: the
-// reduction digit u = (column mod 2^31) * (-M^-1) mod 2^31 clears the low 31
-// bits and the column shifted right by 31 feeds the next one.
+// reduction digit u == (column mod 2^31) * (-M^-1) (mod 2^31) clears the low
+// 31 bits of its column, and the column shifted right by 31 feeds the next.
+// u is used as the full 32-bit product (not reduced mod 2^31): only its
+// residue mod 2^31 matters for the cancellation, and the extra multiple of
+// 2^31 M it adds is covered by the bounds below.
 
 constexpr uint32_t kMask31 = 0x7fffffffu;
 
-// x <- 2^b * REDC(x^2) = 2^b x^2 2^-62 (mod M), for x < 4M, b in {0, 1}.
-// Bounds: d1 < 2^29, so c0 < 2^63, c1 < 2^63, c2 < 2^60; REDC(x^2) <
-// 16M^2/2^62 + M <= 2M for M <= 2^58, and after the doubling x < 4M again.
+// a * b + c with the 64-bit addend fused into one v_mad_u64_u32 (the carry out
+// is not needed: every sum here is below 2^64).
+__device__ __forceinline__ uint64_t mad64(uint32_t a, uint32_t b, uint64_t c) {
+  uint64_t d, cc;
+  asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(d), "=s"(cc) : "v"(a), "v"(b), "v"(c));
+  (void)cc;
+  return d;
+}
+
+// x <- 2^b * REDC(x^2) == 2^b x^2 2^-62 (mod M), for x < 8M, b in {0, 1},
+// odd M < 2^54 with digits m0 < 2^31, m1 < 2^23 and p == -M^-1 (mod 2^31).
+// Bounds: d1 < 2^26, u0, u1 < 2^32; c0 < 2^62 + 2^63, c1 < 2^63.2,
+// c2 < 2^56. The reduction multiplier mu = u0 + u1 2^31 is below
+// 2^63 + 2^32, so REDC(x^2) < 64M^2/2^62 + 2.0001M < 2.26M and after the
+// doubling x < 4.52M < 8M again.
 __device__ __forceinline__ void sqr_redc62(uint32_t &d0, uint32_t &d1, uint32_t b, uint32_t m0,
                                            uint32_t m1, uint32_t p) {
   uint64_t c0 = (uint64_t)d0 * d0;
-  const uint32_t u0 = ((uint32_t)c0 * p) & kMask31;
-  c0 += (uint64_t)u0 * m0;
-  uint64_t c1 = (uint64_t)d0 * (d1 << 1) + (c0 >> 31);
-  c1 += (uint64_t)u0 * m1;
-  const uint32_t u1 = ((uint32_t)c1 * p) & kMask31;
-  c1 += (uint64_t)u1 * m0;
-  uint64_t c2 = (uint64_t)d1 * d1 + (c1 >> 31);
-  c2 += (uint64_t)u1 * m1;
+  const uint32_t u0 = (uint32_t)c0 * p;
+  c0 = mad64(u0, m0, c0);
+  uint64_t c1 = mad64(d0, d1 << 1, c0 >> 31);
+  c1 = mad64(u0, m1, c1);
+  const uint32_t u1 = (uint32_t)c1 * p;
+  c1 = mad64(u1, m0, c1);
+  uint64_t c2 = mad64(d1, d1, c1 >> 31);
+  c2 = mad64(u1, m1, c2);
   c2 <<= b;
   d0 = (uint32_t)c2 & kMask31;
   d1 = (uint32_t)(c2 >> 31);
 }
 
-// floor(2^62 / M) for 2^31 <= M < 2^58, by restoring long division: the
+// floor(2^62 / M) for 2^31 <= M < 2^54, by restoring long division: the
 // quotient has at most 32 bits, and bit s is tried only while M 2^s stays
 // below 2^64.
 __device__ __forceinline__ uint32_t div_2_62(uint64_t M) {

@@ -136,7 +136,8 @@ __device__ __forceinline__ const HeadSeg &find_seg(const HeadSeg *segs, int nseg
 // q = floor(2^62 / M_last) computed once for the run (M_last its largest
 // modulus), so g == 2^62 (mod M) and 0 <= g < (e+1)M with
 // e = floor(2^62/M) - q. The host sizes runs so that (e+1)^2 M < 2^62, which
-// keeps the first squaring inside its bound; after it the residue is below 4M.
+// keeps the first squaring inside its bound (and g < 2^57, so d1 < 2^26);
+// after it the residue is below 8M.
 template <int L>
 __device__ __forceinline__ void lane_run62(uint64_t k0, uint32_t run, uint64_t kend, uint64_t a,
                                            uint64_t b, uint64_t dc, uint64_t step, uint32_t P,
@@ -159,7 +160,8 @@ __device__ __forceinline__ void lane_run62(uint64_t k0, uint32_t run, uint64_t k
     const uint32_t xl = (uint32_t)X, xh = (uint32_t)(X >> 32);
     for (int j = nb - 33; j >= 0; --j) sqr_redc62(d0, d1, (xh >> j) & 1u, m0, m1, p);
     for (int j = (nb < 32 ? nb : 32) - 1; j >= 0; --j) sqr_redc62(d0, d1, (xl >> j) & 1u, m0, m1, p);
-    uint64_t x = d0 + ((uint64_t)d1 << 31);  // 2^(E + 64L) mod M, below 4M
+    uint64_t x = d0 + ((uint64_t)d1 << 31);  // == 2^(E + 64L) (mod M), below 8M
+    x = x >= 4u * M ? x - 4u * M : x;
     x = x >= 2u * M ? x - 2u * M : x;
     x = x >= M ? x - M : x;
     uint64_t t[L];

@@ -18,7 +18,7 @@ struct HeadSeg {
   uint64_t d;          // n - 1
   uint32_t formula, j, P;
   uint32_t acc_off;    // the query's carry-save counters: acc + acc_off
-  uint32_t cls;        // 32: M < 2^31 (R = 2^32), 64: 2^31 <= M < 2^58 (R = 2^62)
+  uint32_t cls;        // 32: M < 2^31 (R = 2^32), 64: 2^31 <= M < 2^54 (R = 2^62)
   uint32_t run;        // indices per lane per chunk; a chunk is 256 * run indices
 };
 

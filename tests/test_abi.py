@@ -60,6 +60,6 @@ def test_invalid_arguments_are_rejected_synchronously():
     assert lib.pi_sum_slice(pb.term_id(0, 4), 10, 0, 5, 64, dummy, null) == E
     assert lib.pi_sum_slice(pb.term_id(1, 0), 10, 6, 5, 64, dummy, null) == E  # k0 > k1
     assert lib.pi_extract(1, 10, 0, dummy, null) == E
-    # moduli from 2^58 up are outside the supported range
+    # moduli from 2^54 up are outside the supported range
     assert lib.pi_extract_ex(1, 2 ** 61, 8, 72, dummy, null, null) == -4
-    assert lib.pi_extract_ex(1, 2 ** 59, 8, 72, dummy, null, null) == -4
+    assert lib.pi_extract_ex(1, 2 ** 55, 8, 72, dummy, null, null) == -4
