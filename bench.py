@@ -39,16 +39,33 @@ def series(formula):
     return [(2, 8, 1), (-1, 2, 1), (0, 8, 5), (-1, 4, 3)], 4
 
 
-def mul32_per_launch(formula, n, P):
+def _pre_bits(run, Mmin, Mmax, a):
+    """Exponent bits the library folds into a class-62 segment's start value
+    (the planner's rule: the start value g 2^v must satisfy (g 2^v)^2 < 2^60 M
+    and g 2^v < 2^56, with g < (2^63 a run / M^2 + 2) M)."""
+    for pre in (3, 2, 1):
+        shift = 2.0 ** ((1 << pre) - 1)
+        good = True
+        for M in (float(Mmin), float(Mmax)):
+            g = (a * run * 2.0 ** 63 / (M * M) + 2.0) * M * shift
+            if g * g >= M * 2.0 ** 60 or g >= 2.0 ** 56:
+                good = False
+        if good:
+            return pre
+    return 0
+
+
+def mul32_per_launch(formula, n, P, run=64):
     """Algorithmic 32-bit multiplies of every head term of one extraction.
 
-    Class 62 (2^31 <= M, R = 2^62, two 31-bit digits): bitlen(X) Montgomery
-    squarings, X = E + 64L - 62, at 9 multiplies each (3 for the square,
-    2 reduction digits, 4 digit-by-modulus products); 12 for -M^-1 mod 2^64;
-    2 for the starting value 2^62 - qM; 7 per limb of the Hensel division
-    (3 for the low product, 4 for the high half of t M).
-    Class 32 (M < 2^31, R = 2^32): 3 per squaring (X = E + 64L - 32), 6 for
-    the inverse, 4 per 64-bit limb of the division.
+    Class 62 (2^31 <= M, R = 2^62, two 31-bit digits): bitlen(X) - pre
+    Montgomery squarings, X = E + 64L - 62, where `pre` top exponent bits
+    (0..3, per modulus range) go into the start value; 9 multiplies per
+    squaring (3 for the square, 2 reduction digits, 4 digit-by-modulus
+    products); 12 for -M^-1 mod 2^64; 2 for the start value 2^62 - qM; 7 per
+    limb of the Hensel division (3 for the low product, 4 for the high half of
+    t M). Class 32 (M < 2^31, R = 2^32): 3 per squaring (X = E + 64L - 32),
+    6 for the inverse, 4 per 64-bit limb of the division.
     """
     rows, step = series(formula)
     L = (P + 63) // 64
@@ -59,12 +76,21 @@ def mul32_per_launch(formula, n, P):
         if d + c < 0:
             continue
         K = (d + c) // step + 1
-        ks = min(K, max(0, -(-(CLASS32_LIMIT - b) // a)))
-        for lo, hi, cls in ((0, ks, 32), (ks, K, 62)):
+
+        def first_k(mlim):
+            return min(K, max(0, -(-(mlim - b) // a)))
+
+        ks, k36 = first_k(CLASS32_LIMIT), first_k(2 ** 36)
+        for lo, hi, cls in ((0, ks, 32), (ks, k36, 62), (k36, K, 62)):
             if lo >= hi:
                 continue
             off = 64 * L - 62 if cls == 62 else 64 * L - 32
-            per_sq, fixed = (9, 14 + 7 * L) if cls == 62 else (3, 6 + 4 * L)
+            if cls == 62:
+                pre = _pre_bits(min(run, max(1, (hi - lo) // 1024)), a * lo + b,
+                                a * (hi - 1) + b, a)
+                per_sq, fixed = 9, 14 + 7 * L - 9 * pre
+            else:
+                per_sq, fixed = 3, 6 + 4 * L
             # X(k) = d + c - step k + off decreases with k; sum bitlen over bands
             k = lo
             while k < hi:

@@ -90,14 +90,20 @@ int make_plan(int formula, uint64_t n, uint32_t w, uint32_t P, uint32_t jmask, u
   return PI_OK;
 }
 
-// Head segments of a plan, split at the class-32/class-64 modulus boundary.
+// Head segments of a plan: split at the class-32/class-62 modulus boundary
+// M = 2^31, and the class-62 range once more at M = 2^36 so that the small
+// moduli (where a lane run's starting value has the most slack to cover) do
+// not limit the run length and start bits of the rest.
 void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &out) {
   for (int j = 0; j < kHJ[qp.formula]; ++j) {
     const HostSeries &s = kHSeries[qp.formula][j];
     const uint64_t kb = qp.hk0[j], ke = qp.hk1[j];
     if (kb >= ke) continue;
-    const uint64_t ks = kClass32Limit > s.b ? (kClass32Limit - s.b + s.a - 1) / s.a : 0;
-    const uint64_t cut = std::min(std::max(ks, kb), ke);
+    auto first_k = [&](uint64_t Mlim) {  // first k with a k + b >= Mlim
+      const uint64_t k = Mlim > s.b ? (Mlim - s.b + s.a - 1) / s.a : 0;
+      return std::min(std::max(k, kb), ke);
+    };
+    const uint64_t cuts[4] = {kb, first_k(kClass32Limit), first_k(1ull << 36), ke};
     HeadSeg g;
     memset(&g, 0, sizeof g);
     g.d = qp.d;
@@ -105,16 +111,11 @@ void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &
     g.j = (uint32_t)j;
     g.P = qp.P;
     g.acc_off = acc_off;
-    if (kb < cut) {
-      g.kb = kb;
-      g.ke = cut;
-      g.cls = 32;
-      out.push_back(g);
-    }
-    if (cut < ke) {
-      g.kb = cut;
-      g.ke = ke;
-      g.cls = 64;
+    for (int c = 0; c < 3; ++c) {
+      if (cuts[c] >= cuts[c + 1]) continue;
+      g.kb = cuts[c];
+      g.ke = cuts[c + 1];
+      g.cls = c == 0 ? 32 : 64;
       out.push_back(g);
     }
   }
@@ -262,17 +263,26 @@ int hip_err(hipError_t e) { return e == hipSuccess ? PI_OK : PI_EDEVICE; }
 // output then stays below 8M) and g < 2^57 (digit bounds); with a margin of
 // 4 and 2 this asks (e+1)^2 M < 2^60 and (e+1) M < 2^56. Both bounds are
 // largest at an end of the modulus range.
-uint32_t safe_run62(uint32_t run, uint64_t Mmin, uint64_t Mmax, uint64_t a) {
+uint32_t safe_run62(uint32_t run, uint64_t Mmin, uint64_t Mmax, uint64_t a, uint32_t pre = 0) {
+  const double shift = std::ldexp(1.0, (int)((1u << pre) - 1u));  // largest 2^v
   auto ok = [&](double r) {
     const double A = std::ldexp((double)a * r, 63);
     for (double M : {(double)Mmin, (double)Mmax}) {
-      const double e1 = A / (M * M) + 2.0;
-      if (e1 * e1 * M >= std::ldexp(1.0, 60) || e1 * M >= std::ldexp(1.0, 56)) return false;
+      const double g = (A / (M * M) + 2.0) * M * shift;
+      if (g * g >= std::ldexp(M, 60) || g >= std::ldexp(1.0, 56)) return false;
     }
     return true;
   };
   while (run > 1 && !ok((double)run)) run = std::max<uint32_t>(1, run / 2);
-  return run;
+  return ok((double)run) ? run : 0;
+}
+
+// Exponent bits a class-62 segment can fold into its start value at `run`
+// (0..3): the largest count whose biggest shift keeps the bounds.
+uint32_t safe_pre62(uint32_t run, uint64_t Mmin, uint64_t Mmax, uint64_t a) {
+  for (uint32_t pre = 3; pre > 0; --pre)
+    if (safe_run62(run, Mmin, Mmax, a, pre) == run) return pre;
+  return 0;
 }
 
 // Number the chunks of the segments and fix each segment's run: about a
@@ -284,7 +294,12 @@ uint64_t number_chunks(std::vector<HeadSeg> &segs, uint32_t run_cap, uint64_t ch
     const HostSeries &s = kHSeries[g.formula][g.j];
     const uint64_t len = g.ke - g.kb;
     uint32_t run = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(run_cap, len / 1024u));
-    if (g.cls == 64) run = safe_run62(run, s.a * g.kb + s.b, s.a * (g.ke - 1) + s.b, s.a);
+    g.pre = 0;
+    if (g.cls == 64) {
+      const uint64_t Mmin = s.a * g.kb + s.b, Mmax = s.a * (g.ke - 1) + s.b;
+      run = std::max<uint32_t>(1, safe_run62(run, Mmin, Mmax, s.a));
+      g.pre = safe_pre62(run, Mmin, Mmax, s.a);
+    }
     g.run = run;
     g.chunk0 = nchunks;
     nchunks += (len + 256ull * run - 1) / (256ull * run);

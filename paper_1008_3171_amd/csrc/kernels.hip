@@ -135,13 +135,14 @@ __device__ __forceinline__ const HeadSeg &find_seg(const HeadSeg *segs, int nseg
 // The ladder starts from an unreduced Montgomery one g = 2^62 - qM, with
 // q = floor(2^62 / M_last) computed once for the run (M_last its largest
 // modulus), so g == 2^62 (mod M) and 0 <= g < (e+1)M with
-// e = floor(2^62/M) - q. The host sizes runs so that (e+1)^2 M < 2^62, which
-// keeps the first squaring inside its bound (and g < 2^57, so d1 < 2^26);
-// after it the residue is below 8M.
+// e = floor(2^62/M) - q. Shifted left by the top `pre` exponent bits v, it is
+// the Montgomery form of 2^v. The host sizes runs and `pre` so that
+// (g 2^v)^2 < 2^60 M and g 2^v < 2^56, which keeps the first squaring inside
+// its bounds; after it the residue is below 8M.
 template <int L>
-__device__ __forceinline__ void lane_run62(uint64_t k0, uint32_t run, uint64_t kend, uint64_t a,
-                                           uint64_t b, uint64_t dc, uint64_t step, uint32_t P,
-                                           uint64_t (&sum)[L]) {
+__device__ __forceinline__ void lane_run62(uint64_t k0, uint32_t run, uint32_t pre, uint64_t kend,
+                                           uint64_t a, uint64_t b, uint64_t dc, uint64_t step,
+                                           uint32_t P, uint64_t (&sum)[L]) {
   const uint64_t dM = 2u * a, dX = 2u * step;
   uint64_t M = a * k0 + b;
   uint64_t X = dc + 64ull * L - 62ull - step * k0;
@@ -151,11 +152,16 @@ __device__ __forceinline__ void lane_run62(uint64_t k0, uint32_t run, uint64_t k
     // lane 0 holds the wave's smallest k, so the largest exponent: if it is
     // past the chunk, so is every lane, and its X bounds the ladder length.
     if (uniform64(k) >= kend) break;
-    const int nb = bitlen64(uniform64(X));
+    const int nb0 = bitlen64(uniform64(X));
     const uint64_t mp = neg_inv64(M);
     const uint32_t m0 = (uint32_t)M & kMask31, m1 = (uint32_t)(M >> 31);
     const uint32_t p = (uint32_t)mp & kMask31;
-    const uint64_t g = (1ull << 62) - (uint64_t)q * M;
+    // the top t exponent bits v go into the start value: g 2^v == 2^(62+v)
+    // is the Montgomery form of 2^v, so t squarings are skipped
+    const int tb = pre < (uint32_t)nb0 ? (int)pre : nb0;
+    const int nb = nb0 - tb;
+    const uint32_t v = (uint32_t)(X >> nb) & ((1u << tb) - 1u);
+    const uint64_t g = ((1ull << 62) - (uint64_t)q * M) << v;
     uint32_t d0 = (uint32_t)g & kMask31, d1 = (uint32_t)(g >> 31);
     const uint32_t xl = (uint32_t)X, xh = (uint32_t)(X >> 32);
     for (int j = nb - 33; j >= 0; --j) sqr_redc62(d0, d1, (xh >> j) & 1u, m0, m1, p);
@@ -222,7 +228,7 @@ __device__ void head_chunks(const HeadSeg *segs, int nseg, uint64_t nchunks,
 #pragma unroll
     for (int i = 0; i < L; ++i) sum[i] = 0;
     if (sg.cls == 64)
-      lane_run62<L>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum);
+      lane_run62<L>(k0, run, sg.pre, kend, sr.a, sr.b, dc, step, sg.P, sum);
     else
       lane_run32<L>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum);
     if (neg) neg_limbs<L>(sum);

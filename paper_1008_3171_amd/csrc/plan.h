@@ -8,7 +8,7 @@
 namespace pibbp {
 
 constexpr int PI_MAX_L = 17;          // ceil(PI_MAX_P / 64)
-constexpr int kMaxArgSegs = 14;       // 7 series x 2 modulus classes
+constexpr int kMaxArgSegs = 21;       // 7 series x 3 modulus ranges
 
 // A range [kb, ke) of head indices (E >= 0) of series j of one query, all of
 // one modulus class; its chunks are numbered chunk0, chunk0 + 1, ...
@@ -20,6 +20,8 @@ struct HeadSeg {
   uint32_t acc_off;    // the query's carry-save counters: acc + acc_off
   uint32_t cls;        // 32: M < 2^31 (R = 2^32), 64: 2^31 <= M < 2^54 (R = 2^62)
   uint32_t run;        // indices per lane per chunk; a chunk is 256 * run indices
+  uint32_t pre;        // class 62: exponent bits taken into the ladder's start value
+  uint32_t pad;
 };
 
 // Segments of a single query, passed by value as a kernel argument.
