@@ -211,16 +211,30 @@ __device__ __forceinline__ void hensel32(uint32_t s, uint32_t M, uint32_t mp32, 
   }
 }
 
-// Clear the low 64L-P bits (P <= 64L).
+// Masks that clear the low 64L-P bits of an L-limb value (P <= 64L); built
+// once per chunk, applied to every term with one AND per 32-bit word.
 template <int L>
-__device__ __forceinline__ void clip_low(uint64_t (&t)[L], uint32_t P) {
+__device__ __forceinline__ void low_masks(uint32_t P, uint64_t (&m)[L]) {
   const uint32_t z = 64u * L - P;
 #pragma unroll
   for (int i = 0; i < L; ++i) {
     const uint32_t lo = 64u * i;
-    if (z >= lo + 64u) t[i] = 0;
-    else if (z > lo) t[i] &= ~0ull << (z - lo);
+    m[i] = z >= lo + 64u ? 0ull : (z > lo ? ~0ull << (z - lo) : ~0ull);
   }
+}
+
+template <int L>
+__device__ __forceinline__ void apply_masks(uint64_t (&t)[L], const uint64_t (&m)[L]) {
+#pragma unroll
+  for (int i = 0; i < L; ++i) t[i] &= m[i];
+}
+
+// Clear the low 64L-P bits (P <= 64L), for the few terms outside the hot loop.
+template <int L>
+__device__ __forceinline__ void clip_low(uint64_t (&t)[L], uint32_t P) {
+  uint64_t m[L];
+  low_masks<L>(P, m);
+  apply_masks<L>(t, m);
 }
 
 }  // namespace pibbp

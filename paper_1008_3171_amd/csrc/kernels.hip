@@ -147,6 +147,8 @@ __device__ __forceinline__ void lane_run62(uint64_t k0, uint32_t run, uint32_t p
   uint64_t M = a * k0 + b;
   uint64_t X = dc + 64ull * L - 62ull - step * k0;
   const uint32_t q = div_2_62(M + dM * (run - 1u));
+  uint64_t msk[L];
+  low_masks<L>(P, msk);
   for (uint32_t i = 0; i < run; ++i, M += dM, X -= dX) {
     const uint64_t k = k0 + 2ull * i;
     // lane 0 holds the wave's smallest k, so the largest exponent: if it is
@@ -172,7 +174,7 @@ __device__ __forceinline__ void lane_run62(uint64_t k0, uint32_t run, uint32_t p
     x = x >= M ? x - M : x;
     uint64_t t[L];
     hensel64<L>(x, M, mp, t);
-    clip_low<L>(t, P);
+    apply_masks<L>(t, msk);
     if (k < kend) add_limbs<L>(sum, t);
   }
 }
@@ -183,6 +185,8 @@ template <int L>
 __device__ __forceinline__ void lane_run32(uint64_t k0, uint32_t run, uint64_t kend, uint64_t a,
                                            uint64_t b, uint64_t dc, uint64_t step, uint32_t P,
                                            uint64_t (&sum)[L]) {
+  uint64_t msk[L];
+  low_masks<L>(P, msk);
   for (uint32_t i = 0; i < run; ++i) {
     const uint64_t k = k0 + 2ull * i;
     const uint64_t kl0 = uniform64(k);
@@ -200,7 +204,7 @@ __device__ __forceinline__ void lane_run32(uint64_t k0, uint32_t run, uint64_t k
     for (int j = (nb < 32 ? nb : 32) - 1; j >= 0; --j) x = sqr_redc32(x, (xl >> j) & 1u, M32, mp);
     uint64_t t[L];
     hensel32<L>(x, M32, mp, t);
-    clip_low<L>(t, P);
+    apply_masks<L>(t, msk);
     if (active && M != 1) add_limbs<L>(sum, t);
   }
 }
