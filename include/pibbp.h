@@ -102,6 +102,25 @@ PI_API int pi_extract_ex(int formula, uint64_t n, uint32_t nbits, uint32_t P, ui
 PI_API int pi_sum_slice(int term, uint64_t n, uint64_t k0, uint64_t k1, uint32_t P, uint64_t *out,
                  hipStream_t stream);
 
+/* pi_sum_slice that also reports, in status->nterms, how many indices of
+ * [k0, k1) are summed before the series' stop index (every head index, and
+ * the tail indices whose truncated term is nonzero); status->code is PI_OK.
+ * Summed over a partition of a query's index set these counts give the N of
+ * pi_extract_ex. status: device pi_status or NULL. */
+PI_API int pi_sum_slice_ex(int term, uint64_t n, uint64_t k0, uint64_t k1, uint32_t P,
+                           uint64_t *out, pi_status *status, hipStream_t stream);
+
+/* The sum of `count` partial sums kept between calls (section 4 persists the
+ * partial sums of jobs and adds them at the end): parts is a device array of
+ * count x ceil(P/64) left-aligned limbs, e.g. pi_sum_slice outputs over a
+ * partition of a query's index set. out receives their sum mod 2^P, and
+ * status (device, may be NULL) its certification for the top nbits with
+ * N = nterms and nseries series (4 for BBP, 7 for Bellard), as in
+ * pi_extract_ex. */
+PI_API int pi_combine(const uint64_t *parts, int count, uint32_t P, uint32_t nbits,
+                      uint32_t nseries, uint64_t nterms, uint64_t *out, pi_status *status,
+                      hipStream_t stream);
+
 /* A query of a batch. out_offset is in uint64 limbs from the batch's `out`;
  * the query writes ceil(P/64) limbs there. */
 typedef struct {

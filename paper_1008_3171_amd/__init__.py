@@ -276,3 +276,43 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def sum_slice_ex(term: int, n: int, k0: int, k1: int, P: int, out=None, status=None, stream=None):
+    """pi_sum_slice_ex: (limbs, status); status holds N, the indices summed."""
+    torch = _torch()
+    lib = load()
+    lib.pi_sum_slice_ex.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                    ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p]
+    lib.pi_sum_slice_ex.restype = ctypes.c_int
+    if out is None:
+        out = torch.zeros(limbs(P), dtype=torch.int64, device="cuda")
+    if status is None:
+        status = torch.zeros(4, dtype=torch.int32, device="cuda")
+    rc = lib.pi_sum_slice_ex(term, n, k0, k1, P, ctypes.c_void_p(out.data_ptr()),
+                             ctypes.c_void_p(status.data_ptr()), _stream(stream))
+    if rc != 0:
+        raise PiError(rc, "pi_sum_slice_ex")
+    return out, status
+
+
+def combine(parts, count: int, P: int, nbits: int, nseries: int, nterms: int, out=None,
+            status=None, stream=None):
+    """pi_combine over a device int64 tensor of count x limbs(P) partial sums."""
+    torch = _torch()
+    lib = load()
+    lib.pi_combine.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32,
+                               ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p,
+                               ctypes.c_void_p, ctypes.c_void_p]
+    lib.pi_combine.restype = ctypes.c_int
+    if out is None:
+        out = torch.zeros(limbs(P), dtype=torch.int64, device="cuda")
+    if status is None:
+        status = torch.zeros(4, dtype=torch.int32, device="cuda")
+    rc = lib.pi_combine(ctypes.c_void_p(parts.data_ptr()), count, P, nbits, nseries, nterms,
+                        ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(status.data_ptr()),
+                        _stream(stream))
+    if rc != 0:
+        raise PiError(rc, "pi_combine")
+    return out, status

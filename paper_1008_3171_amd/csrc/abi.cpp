@@ -121,7 +121,7 @@ void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &
   }
 }
 
-FinQuery fin_query(const QueryPlan &qp, uint64_t out_off, bool want_status, uint32_t sidx,
+FinQuery fin_query(const QueryPlan &qp, uint64_t out_off, uint32_t status_mode, uint32_t sidx,
                    uint32_t acc_off) {
   FinQuery f;
   memset(&f, 0, sizeof f);
@@ -136,7 +136,7 @@ FinQuery fin_query(const QueryPlan &qp, uint64_t out_off, bool want_status, uint
   f.P = qp.P;
   f.w = qp.w;
   f.Lq = qp.Lq;
-  f.want_status = want_status ? 1u : 0u;
+  f.want_status = status_mode;
   f.status_idx = sidx;
   f.acc_off = acc_off;
   return f;
@@ -314,7 +314,8 @@ uint32_t min_run_cap(uint64_t head_terms) {
 }
 
 // Launch everything for one planned query (head segments passed by value).
-int run_single(const QueryPlan &qp, uint64_t *out, pi_status *status, hipStream_t st) {
+int run_single(const QueryPlan &qp, uint64_t *out, pi_status *status, uint32_t mode,
+               hipStream_t st) {
   std::vector<HeadSeg> segs;
   head_segments(qp, 0, segs);
   const int grid_max = resident_grid();
@@ -332,7 +333,7 @@ int run_single(const QueryPlan &qp, uint64_t *out, pi_status *status, hipStream_
     const int grid = (int)std::min<uint64_t>(nchunks, (uint64_t)grid_max);
     if (int e = hip_err(launch_head_args(Lk, tab, nchunks, grid, acc, st))) return e;
   }
-  FinQuery fq = fin_query(qp, 0, status != nullptr, 0, 0);
+  FinQuery fq = fin_query(qp, 0, status != nullptr ? mode : 0u, 0, 0);
   return hip_err(launch_finalize(Lk, fq, nullptr, 1, acc, out, status, st));
 }
 
@@ -376,7 +377,7 @@ int plan_batch(const pi_query *q, int count, BatchPlan *bp) {
     const uint32_t cap = std::max(pick_run(qp.nhead, grid_max), min_run_cap(qp.nhead));
     c.nchunks += number_chunks(segs, cap, c.nchunks);
     c.segs.insert(c.segs.end(), segs.begin(), segs.end());
-    c.fins.push_back(fin_query(qp, q[i].out_offset, true, (uint32_t)i, local * 2u * (uint32_t)qp.Lk));
+    c.fins.push_back(fin_query(qp, q[i].out_offset, 1u, (uint32_t)i, local * 2u * (uint32_t)qp.Lk));
   }
   size_t off = 0;
   for (ClassPlan &c : bp->cls) {
@@ -450,7 +451,7 @@ int pi_extract_ex(int formula, uint64_t n, uint32_t nbits, uint32_t P, uint64_t 
   if (!out) return PI_EINVAL;
   QueryPlan qp;
   if (int e = make_plan(formula, n, nbits, P, 0x7fu, 0, UINT64_MAX, &qp)) return e;
-  return run_single(qp, out, status, stream);
+  return run_single(qp, out, status, 1u, stream);
 }
 
 int pi_extract(int formula, uint64_t n, uint32_t nbits, uint64_t *out, hipStream_t stream) {
@@ -465,7 +466,26 @@ int pi_sum_slice(int term, uint64_t n, uint64_t k0, uint64_t k1, uint32_t P, uin
   if ((formula != PI_BBP && formula != PI_BELLARD) || j >= kHJ[formula]) return PI_EINVAL;
   QueryPlan qp;
   if (int e = make_plan(formula, n, P, P, 1u << j, k0, k1, &qp)) return e;
-  return run_single(qp, out, nullptr, stream);
+  return run_single(qp, out, nullptr, 0u, stream);
+}
+
+int pi_sum_slice_ex(int term, uint64_t n, uint64_t k0, uint64_t k1, uint32_t P, uint64_t *out,
+                    pi_status *status, hipStream_t stream) {
+  if (!out || term < 0) return PI_EINVAL;
+  const int formula = term / 16, j = term % 16;
+  if ((formula != PI_BBP && formula != PI_BELLARD) || j >= kHJ[formula]) return PI_EINVAL;
+  QueryPlan qp;
+  if (int e = make_plan(formula, n, P, P, 1u << j, k0, k1, &qp)) return e;
+  return run_single(qp, out, status, 2u, stream);
+}
+
+int pi_combine(const uint64_t *parts, int count, uint32_t P, uint32_t nbits, uint32_t nseries,
+               uint64_t nterms, uint64_t *out, pi_status *status, hipStream_t stream) {
+  if (!out || count < 0 || (count > 0 && !parts) || P == 0 || P > PI_MAX_P || nbits == 0 ||
+      nbits > P)
+    return PI_EINVAL;
+  return hip_err(launch_combine(parts, count, (int)((P + 63u) / 64u), P, nbits, nterms, nseries,
+                                out, status, stream));
 }
 
 uint64_t pi_head_terms(int formula, uint64_t n) {

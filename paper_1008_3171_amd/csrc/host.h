@@ -29,7 +29,7 @@ void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &
 uint64_t number_chunks(std::vector<HeadSeg> &segs, uint32_t run_cap, uint64_t chunk_base);
 uint32_t pick_run(uint64_t head_terms, int grid);
 uint32_t min_run_cap(uint64_t head_terms);
-FinQuery fin_query(const QueryPlan &qp, uint64_t out_off, bool want_status, uint32_t sidx,
+FinQuery fin_query(const QueryPlan &qp, uint64_t out_off, uint32_t status_mode, uint32_t sidx,
                    uint32_t acc_off);
 int resident_grid();
 int hip_err(hipError_t e);

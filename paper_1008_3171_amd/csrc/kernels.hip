@@ -293,6 +293,75 @@ __device__ void tail_term(int64_t E, uint64_t M, uint32_t P, uint64_t (&t)[L]) {
   clip_low<L>(t, P);
 }
 
+// Certification (section 3.1, adapted to truncated terms). S is given in
+// Lq left-aligned limbs (z = 64Lq - P zero bits at the bottom). G = the low
+// g = 64Lq - w bits, B = (N + 2J) 2^z; the top w bits are proven bits of pi
+// iff G >= B and G + B <= 2^g. Both tests run over Lq + 1 limbs.
+// mode 1: certify; mode 2: report N only (code PI_OK), for slices.
+__device__ pi_status certify(const uint64_t *Sq, int Lq, uint32_t P, uint32_t w, uint64_t N,
+                             uint64_t J, uint32_t mode) {
+  pi_status st;
+  st.reserved = 0;
+  st.nterms = N;
+  if (mode == 2) {
+    st.code = PI_OK;
+    return st;
+  }
+  const uint32_t z = 64u * (uint32_t)Lq - P, g = 64u * (uint32_t)Lq - w;
+  const uint64_t Bn = N + 2ull * J;
+  uint64_t Bv[PI_MAX_L + 1], Gv[PI_MAX_L + 1], Sum[PI_MAX_L + 1], Pg[PI_MAX_L + 1];
+  for (int i = 0; i <= Lq; ++i) {
+    Bv[i] = 0;
+    Pg[i] = 0;
+    const uint32_t lo = 64u * (uint32_t)i;
+    uint64_t gi = 0;
+    if (i < Lq) gi = g >= lo + 64u ? Sq[i] : (g > lo ? Sq[i] & ((1ull << (g - lo)) - 1ull) : 0ull);
+    Gv[i] = gi;
+    if (g >= lo && g < lo + 64u) Pg[i] = 1ull << (g - lo);
+  }
+  Bv[0] = Bn << z;
+  if (z) Bv[1] = Bn >> (64u - z);
+  unsigned long long c1 = 0, c2 = 0, c3 = 0;
+  for (int i = 0; i <= Lq; ++i) {
+    (void)__builtin_subcll(Gv[i], Bv[i], c1, &c1);      // G - B: borrow out => G < B
+    Sum[i] = __builtin_addcll(Gv[i], Bv[i], c2, &c2);  // G + B
+  }
+  for (int i = 0; i <= Lq; ++i) (void)__builtin_subcll(Pg[i], Sum[i], c3, &c3);  // 2^g - (G+B)
+  st.code = (c1 == 0 && c2 == 0 && c3 == 0) ? PI_OK : PI_UNCERTAIN;
+  return st;
+}
+
+// Sum of `count` partial sums (each Lq left-aligned limbs, mod 2^(64Lq)) and
+// the certification of the total with N = nterms: the final sum over jobs of
+// section 4, for sums kept outside the device between calls. One workgroup.
+__global__ __launch_bounds__(256) void combine_kernel(const uint64_t *parts, int count, int Lq,
+                                                     uint32_t P, uint32_t w, uint64_t nterms,
+                                                     uint32_t J, uint64_t *out, pi_status *status) {
+  __shared__ unsigned long long col[2 * PI_MAX_L];
+  const uint32_t tid = threadIdx.x;
+  if (tid < 2u * PI_MAX_L) col[tid] = 0;
+  __syncthreads();
+  // carry-save: every 32-bit half of every part goes into its column
+  for (int i = tid; i < count * 2 * Lq; i += 256) {
+    const int part = i / (2 * Lq), h = i % (2 * Lq);
+    const uint64_t limb = parts[(uint64_t)part * Lq + h / 2];
+    atomicAdd(&col[h], (unsigned long long)(uint32_t)(h & 1 ? limb >> 32 : limb));
+  }
+  __syncthreads();
+  if (tid != 0) return;
+  uint64_t S[PI_MAX_L];
+  unsigned long long carry = 0;
+  for (int i = 0; i < Lq; ++i) {
+    const unsigned long long lo = col[2 * i] + carry;
+    carry = (lo >> 32) + (lo < carry ? (1ull << 32) : 0ull);
+    const unsigned long long hi = col[2 * i + 1] + carry;
+    carry = (hi >> 32) + (hi < carry ? (1ull << 32) : 0ull);
+    S[i] = (lo & 0xffffffffull) | (hi << 32);
+  }
+  for (int i = 0; i < Lq; ++i) out[i] = S[i];
+  if (status) *status = certify(S, Lq, P, w, nterms, J, 1);
+}
+
 template <int L>
 __global__ __launch_bounds__(256) void finalize_kernel(FinQuery single, const FinQuery *qs,
                                                        const unsigned long long *acc,
@@ -366,37 +435,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinQuery single, const Fi
   uint64_t *o = out + q.out_off;
   for (int i = 0; i < Lq; ++i) o[i] = Sq[i];
   if (!q.want_status) return;
-  // Certification (section 3.1, adapted to truncated terms). S is
-  // left-aligned: z = 64Lq - P zero bits at the bottom. G = the low
-  // g = 64Lq - w bits, B = (N + 2J) 2^z; certified iff G >= B and
-  // G + B <= 2^g. Both sides are compared over Lq + 1 limbs.
-  const uint64_t N = q.nhead + nz_total;
-  const uint32_t z = 64u * (uint32_t)Lq - q.P, g = 64u * (uint32_t)Lq - q.w;
-  const uint64_t Bn = N + 2ull * (uint64_t)J;
-  uint64_t Bv[PI_MAX_L + 1], Gv[PI_MAX_L + 1], Sum[PI_MAX_L + 1], Pg[PI_MAX_L + 1];
-  for (int i = 0; i <= Lq; ++i) {
-    Bv[i] = 0;
-    Pg[i] = 0;
-    const uint32_t lo = 64u * (uint32_t)i;
-    uint64_t gi = 0;
-    if (i < Lq) gi = g >= lo + 64u ? Sq[i] : (g > lo ? Sq[i] & ((1ull << (g - lo)) - 1ull) : 0ull);
-    Gv[i] = gi;
-    if (g >= lo && g < lo + 64u) Pg[i] = 1ull << (g - lo);
-  }
-  Bv[0] = Bn << z;
-  if (z) Bv[1] = Bn >> (64u - z);
-  unsigned long long c1 = 0, c2 = 0, c3 = 0;
-  for (int i = 0; i <= Lq; ++i) {
-    (void)__builtin_subcll(Gv[i], Bv[i], c1, &c1);      // G - B: borrow out => G < B
-    Sum[i] = __builtin_addcll(Gv[i], Bv[i], c2, &c2);  // G + B
-  }
-  for (int i = 0; i <= Lq; ++i) (void)__builtin_subcll(Pg[i], Sum[i], c3, &c3);  // 2^g - (G+B)
-  const bool ok = c1 == 0 && c2 == 0 && c3 == 0;
-  pi_status st;
-  st.code = ok ? PI_OK : PI_UNCERTAIN;
-  st.reserved = 0;
-  st.nterms = N;
-  status[q.status_idx] = st;
+  status[q.status_idx] = certify(Sq, Lq, q.P, q.w, q.nhead + nz_total, (uint64_t)J,
+                                  q.want_status);
 }
 
 // ---- launchers ---------------------------------------------------------------
@@ -454,6 +494,14 @@ hipError_t launch_finalize(int Lk, const FinQuery &single, const FinQuery *qs, i
   PIBBP_DISPATCH(Lk, C)
 #undef C
 }
+hipError_t launch_combine(const uint64_t *parts, int count, int Lq, uint32_t P, uint32_t w,
+                          uint64_t nterms, uint32_t J, uint64_t *out, pi_status *status,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(256), 0, st, parts, count, Lq, P, w, nterms, J,
+                     out, status);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(unsigned long long *p, uint64_t n, hipStream_t st) {
   if (n == 0) return hipSuccess;
   int grid = (int)((n + 255) / 256);

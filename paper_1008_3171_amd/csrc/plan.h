@@ -39,7 +39,8 @@ struct FinQuery {
   uint64_t out_off;    // in limbs
   uint64_t tk0[7], tk1[7];
   uint32_t formula, P, w, Lq;
-  uint32_t want_status, status_idx;
+  uint32_t want_status;  // 0: none, 1: certify, 2: report N only
+  uint32_t status_idx;
   uint32_t acc_off;    // the query's counters: acc + acc_off
   uint32_t pad;
 };
@@ -52,5 +53,8 @@ hipError_t launch_finalize(int Lk, const FinQuery &single, const FinQuery *qs, i
                            const unsigned long long *acc, uint64_t *out, pi_status *status,
                            hipStream_t st);
 hipError_t launch_zero(unsigned long long *p, uint64_t n, hipStream_t st);
+hipError_t launch_combine(const uint64_t *parts, int count, int Lq, uint32_t P, uint32_t w,
+                          uint64_t nterms, uint32_t J, uint64_t *out, pi_status *status,
+                          hipStream_t st);
 
 }  // namespace pibbp

@@ -187,7 +187,7 @@ int pi_server_step(pi_server *s, uint32_t *finished) {
   std::map<int, std::vector<FinQuery>> fins_by_class;
   for (size_t r = 0; r < finishing.size(); ++r) {
     const Active &a = s->active[finishing[r]];
-    fins_by_class[a.qp.Lk].push_back(fin_query(a.qp, (uint64_t)r * PI_MAX_L, true, (uint32_t)r,
+    fins_by_class[a.qp.Lk].push_back(fin_query(a.qp, (uint64_t)r * PI_MAX_L, 1u, (uint32_t)r,
                                                a.slot * kSlotCounters));
   }
   size_t nsegs = 0, nfins = 0;

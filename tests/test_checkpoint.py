@@ -1,0 +1,31 @@
+"""Checkpoint bookkeeping (CPU): the pieces partition every series' index
+range exactly, the file round-trips, and a damaged piece is recomputed."""
+import json
+
+from paper_1008_3171_amd import checkpoint
+
+
+def test_plan_partitions_each_series():
+    ck = checkpoint.plan(1, 10 ** 9 + 1, 256, 320, 5)
+    kmax = (10 ** 9 + 1 + 320) // 10 + 2
+    for j in range(7):
+        rs = sorted((it["k0"], it["k1"]) for it in ck["items"] if it["j"] == j)
+        assert rs[0][0] == 0 and rs[-1][1] == kmax
+        assert all(a[1] == b[0] for a, b in zip(rs, rs[1:]))
+    assert len(checkpoint.plan(0, 1000, 8, 72, 3)["items"]) == 12
+
+
+def test_roundtrip_and_damaged_piece_is_recomputed(tmp_path):
+    path = str(tmp_path / "ck.json")
+    ck = checkpoint.plan(1, 12345, 64, 128, 2)
+    it = ck["items"][3]
+    it["S"], it["N"], it["seconds"] = "1234abcd", 77, 0.1
+    it["hash"] = checkpoint._digest(it)
+    checkpoint.save(ck, path)
+    back = checkpoint.load(path)
+    assert back["items"][3]["S"] == "1234abcd" and 3 not in checkpoint.pending(back)
+    raw = json.load(open(path))
+    raw["items"][3]["S"] = "1234abce"                 # one flipped bit
+    json.dump(raw, open(path, "w"))
+    back = checkpoint.load(path)
+    assert 3 in checkpoint.pending(back)

@@ -1,0 +1,68 @@
+"""Checkpointed extraction (partial sums persisted between calls, summed and
+certified on the device) equals the one-call extraction bit for bit; slice
+counts N equal the oracle's."""
+import os
+import random
+
+import pytest
+
+import oracle
+import paper_1008_3171_amd as pb
+from conftest import hex_bits, read_golden
+from paper_1008_3171_amd import checkpoint
+
+pytestmark = pytest.mark.gpu
+
+
+def alone(f, n, w, P):
+    out, st = pb.extract(f, n, w, P)
+    code, N = pb.status_of(st)
+    return pb.to_int(out, P), code, N
+
+
+def test_slice_counts_match_oracle():
+    rng = random.Random(8)
+    for f in (pb.BBP, pb.BELLARD):
+        for j in range(4 if f == pb.BBP else 7):
+            n = rng.randrange(1, 10 ** 6)
+            P = rng.choice([64, 320])
+            kmax = (n + P) // (4 if f == pb.BBP else 10) + 2
+            k0 = rng.randrange(0, kmax)
+            k1 = rng.randrange(k0, kmax + 50)
+            out, st = pb.sum_slice_ex(pb.term_id(f, j), n, k0, k1, P)
+            S, N = oracle.sum_slice(f, j, n - 1, k0, k1, P, 8)
+            assert (pb.to_int(out, P), pb.status_of(st)) == (S, (0, N))
+
+
+def test_interrupted_and_resumed_extraction_equals_one_call(tmp_path):
+    path = str(tmp_path / "ck.json")
+    for f, n, w, P in ((pb.BELLARD, 10 ** 8 + 1, 256, 320), (pb.BBP, 7654321, 64, 96)):
+        ck = checkpoint.plan(f, n, w, P, 3)
+        checkpoint.save(ck, path)
+        assert checkpoint.run(checkpoint.load(path), path, 1e9, max_pieces=5) == 5
+        ck = checkpoint.load(path)                       # "a later process" resumes
+        assert len(checkpoint.pending(ck)) == len(ck["items"]) - 5
+        checkpoint.run(ck, path, 1e9)
+        assert checkpoint.finish(checkpoint.load(path)) == alone(f, n, w, P)
+
+
+def test_combine_certifies_like_extract():
+    # an uncertain case: too few guard bits for N
+    f, n, w, P = pb.BELLARD, 100_001, 60, 64
+    ck = checkpoint.plan(f, n, w, P, 2)
+    checkpoint.run(ck, None, 1e9)
+    got = checkpoint.finish(ck)
+    assert got == alone(f, n, w, P)
+    assert got[1] == pb.PI_UNCERTAIN
+
+
+@pytest.mark.skipif(not os.environ.get("PIBBP_M13"),
+                    reason="7*10^12 terms, ~2.5 min of GPU; set PIBBP_M13=1 to run")
+def test_table_2_2_row_m13_checkpointed(tmp_path):
+    row = [r for r in read_golden("table_2_2.txt") if r[0] == "13"][0]
+    n = int(row[1])
+    ck = checkpoint.plan(pb.BELLARD, n, 256, 320, 4)
+    checkpoint.run(ck, str(tmp_path / "m13.json"), 1e9)
+    S, code, N = checkpoint.finish(ck)
+    assert code == pb.PI_OK
+    assert S >> 64 == hex_bits(row[3], 256)
