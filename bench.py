@@ -235,6 +235,33 @@ def paper_slice(pb, torch):
             "terms_per_s": 7 * (k1 - k0) / s}
 
 
+def other_configs(pb, torch):
+    """Configs 1 and 2 as single queries: Bellard n = 10^6 (64 bits, P = 96),
+    Bellard and BBP at n = 10^10 (256 bits, P = 320)."""
+    stream = torch.cuda.current_stream()
+    rows = {}
+    for name, f, n, w, P in (("config1_bellard_n1e6", pb.BELLARD, 10 ** 6, 64, 96),
+                             ("config2_bellard_n1e10", pb.BELLARD, 10 ** 10, 256, 320),
+                             ("config2_bbp_n1e10", pb.BBP, 10 ** 10, 256, 320)):
+        out = torch.zeros(pb.limbs(P), dtype=torch.int64, device="cuda")
+        st = torch.zeros(4, dtype=torch.int32, device="cuda")
+        pb.extract(f, n, w, P, out=out, status=st, stream=stream)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        pb.extract(f, n, w, P, out=out, status=st, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3
+        terms = pb.head_terms(f, n)
+        S = pb.to_int(out, P)
+        rows[name] = {"seconds": sec, "head_terms": terms, "terms_per_s": terms / sec,
+                      "certified": pb.status_of(st)[0] == pb.PI_OK,
+                      "hex": "%0*x" % ((w + 3) // 4, S >> (P - w))}
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,6 +274,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--measure-peak", action="store_true",
+                    help="run the VALU issue-rate probe and report its rates")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device twice (a plain copy "
                          "kernel of known size, to calibrate memory counters)")
@@ -326,7 +355,13 @@ def main():
         h = re.search(r"^12 \d+ \d+ ([0-9A-F]+)$", row, re.M).group(1)
         ref = int(h, 16) >> (4 * len(h) - 255)
         rec["matches_table_2_2_m12"] = ((S >> (P - w)) & ((1 << 255) - 1)) == ref
+    if args.measure_peak:
+        import subprocess
+        probe = os.path.join(ROOT, "paper_1008_3171_amd", "probe", "valu_rates")
+        res = subprocess.run([probe], capture_output=True, text=True, timeout=120, check=True)
+        rec["valu_rates"] = [json.loads(l) for l in res.stdout.splitlines() if l.strip()]
     if not args.no_batch:
+        rec["other_configs"] = other_configs(pb, torch)
         rec["batch"] = batch_vs_loop(pb, torch)
         rec["paper_slice"] = paper_slice(pb, torch)
     if not args.no_serving:

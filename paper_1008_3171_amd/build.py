@@ -36,6 +36,22 @@ def hipcc() -> str:
     return "hipcc"
 
 
+PROBE_SRC = os.path.join(PKG, "probe", "valu_rates.hip")
+PROBE_BIN = os.path.join(PKG, "probe", "valu_rates")
+
+
+def build_probe(verbose: bool = False) -> str:
+    """The VALU issue-rate probe (a standalone program, not part of the library)."""
+    tmp = PROBE_BIN + ".tmp%d" % os.getpid()
+    cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-o", tmp, PROBE_SRC]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + res.stderr)
+    os.replace(tmp, PROBE_BIN)
+    return PROBE_BIN
+
+
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc()] + HIPCC_FLAGS + [
@@ -53,6 +69,7 @@ def build(verbose: bool = False) -> str:
     if verbose and err.strip():
         print(err, file=sys.stderr)
     os.replace(tmp, LIB)
+    build_probe(verbose)
     return LIB
 
 

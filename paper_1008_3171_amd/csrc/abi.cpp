@@ -90,11 +90,14 @@ int make_plan(int formula, uint64_t n, uint32_t w, uint32_t P, uint32_t jmask, u
   return PI_OK;
 }
 
-// Head segments of a plan: split at the class-32/class-62 modulus boundary
-// M = 2^31, and the class-62 range once more at M = 2^36 so that the small
-// moduli (where a lane run's starting value has the most slack to cover) do
-// not limit the run length and start bits of the rest.
+// Head segments of a plan, split by modulus range: below 2^22 (R = 2^32,
+// Montgomery one by doublings), [2^22, 2^29) (R = 2^32, lazy residues),
+// [2^29, 2^31) (R = 2^32), [2^31, 2^36) and from 2^36 (R = 2^62; split so
+// that the small moduli, where a lane run's starting value has the most slack
+// to cover, do not limit the run length and start bits of the rest).
 void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &out) {
+  static const uint64_t kLim[4] = {1ull << 22, 1ull << 29, kClass32Limit, 1ull << 36};
+  static const uint32_t kCls[5] = {22, 29, 31, 64, 64};
   for (int j = 0; j < kHJ[qp.formula]; ++j) {
     const HostSeries &s = kHSeries[qp.formula][j];
     const uint64_t kb = qp.hk0[j], ke = qp.hk1[j];
@@ -103,7 +106,8 @@ void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &
       const uint64_t k = Mlim > s.b ? (Mlim - s.b + s.a - 1) / s.a : 0;
       return std::min(std::max(k, kb), ke);
     };
-    const uint64_t cuts[4] = {kb, first_k(kClass32Limit), first_k(1ull << 36), ke};
+    const uint64_t cuts[6] = {kb, first_k(kLim[0]), first_k(kLim[1]), first_k(kLim[2]),
+                              first_k(kLim[3]), ke};
     HeadSeg g;
     memset(&g, 0, sizeof g);
     g.d = qp.d;
@@ -111,11 +115,11 @@ void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &
     g.j = (uint32_t)j;
     g.P = qp.P;
     g.acc_off = acc_off;
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < 5; ++c) {
       if (cuts[c] >= cuts[c + 1]) continue;
       g.kb = cuts[c];
       g.ke = cuts[c + 1];
-      g.cls = c == 0 ? 32 : 64;
+      g.cls = kCls[c];
       out.push_back(g);
     }
   }
@@ -295,6 +299,12 @@ uint64_t number_chunks(std::vector<HeadSeg> &segs, uint32_t run_cap, uint64_t ch
     const uint64_t len = g.ke - g.kb;
     uint32_t run = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(run_cap, len / 1024u));
     g.pre = 0;
+    if (g.cls == 29 || g.cls == 31) {
+      // the start value 2^32 - qM stays below 2M when 2^32 2a run < Mmin^2
+      const uint64_t Mmin = s.a * g.kb + s.b;
+      const uint64_t lim = (uint64_t)(((unsigned __int128)Mmin * Mmin >> 32) / (2u * s.a));
+      run = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(run, lim));
+    }
     if (g.cls == 64) {
       const uint64_t Mmin = s.a * g.kb + s.b, Mmax = s.a * (g.ke - 1) + s.b;
       run = std::max<uint32_t>(1, safe_run62(run, Mmin, Mmax, s.a));

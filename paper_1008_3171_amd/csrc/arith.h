@@ -156,6 +156,32 @@ __device__ __forceinline__ uint32_t sqr_redc32(uint32_t x, uint32_t b, uint32_t 
   return min(r, r - M);
 }
 
+// Lazy variant for M < 2^29: residues stay in [0, 2M). With x < 2M,
+// y = x 2^b < 4M < 2^31, T = x y < 8M^2 and T + qM < 2^62, so the result is
+// below 8M^2/2^32 + M <= 2M and no subtraction is needed.
+__device__ __forceinline__ uint32_t sqr_redc32_lazy(uint32_t x, uint32_t b, uint32_t M,
+                                                    uint32_t mp) {
+  const uint32_t y = x << b;
+  const uint64_t T = (uint64_t)x * y;
+  const uint32_t q = (uint32_t)T * mp;
+  return (uint32_t)((T + (uint64_t)q * M) >> 32);
+}
+
+// floor(2^32 / M) for 2^22 <= M < 2^31 (restoring division; at most 11
+// quotient bits).
+__device__ __forceinline__ uint32_t div_2_32(uint32_t M) {
+  uint64_t r = 1ull << 32;
+  uint32_t q = 0;
+  for (int s = 10; s >= 0; --s) {
+    const uint64_t ms = (uint64_t)M << s;
+    if (r >= ms) {
+      r -= ms;
+      q |= 1u << s;
+    }
+  }
+  return q;
+}
+
 // 2^32 mod M, M odd, 3 <= M < 2^31.
 __device__ __forceinline__ uint32_t mont_one32(uint32_t M) {
   int bl = bitlen32(M);

@@ -179,33 +179,53 @@ __device__ __forceinline__ void lane_run62(uint64_t k0, uint32_t run, uint32_t p
   }
 }
 
-// Class-32 terms of one lane (3 <= M < 2^31, except the M = 1 term of k = 0,
-// whose value 2^E mod 1 = 0 is skipped); X = E + 64L - 32.
-template <int L>
+// Class-32 terms of one lane (R = 2^32; X = E + 64L - 32). Three variants,
+// chosen per segment by the modulus range:
+//  * kLazy (M < 2^29): residues in [0, 2M), 4 instructions per step plus the
+//    exponent bit; otherwise (2^29 <= M < 2^31) residues in [0, M).
+//  * kRunStart (M >= 2^22): the Montgomery one is g = 2^32 - qM with
+//    q = floor(2^32 / M_last) for the lane's run; the host keeps runs short
+//    enough that g < 2M. Below 2^22 it comes from doublings of 2^bl - M.
+// The k = 0 term of a b = 1 series has M = 1 and value 2^E mod 1 = 0; it is
+// computed on garbage and not added.
+template <int L, bool kLazy, bool kRunStart>
 __device__ __forceinline__ void lane_run32(uint64_t k0, uint32_t run, uint64_t kend, uint64_t a,
                                            uint64_t b, uint64_t dc, uint64_t step, uint32_t P,
                                            uint64_t (&sum)[L]) {
+  const uint64_t dM = 2u * a, dX = 2u * step;
+  uint64_t M = a * k0 + b;
+  uint64_t X = dc + 64ull * L - 32ull - step * k0;
+  uint32_t q = 0;
+  if (kRunStart) q = div_2_32((uint32_t)(M + dM * (run - 1u)));
   uint64_t msk[L];
   low_masks<L>(P, msk);
-  for (uint32_t i = 0; i < run; ++i) {
+  for (uint32_t i = 0; i < run; ++i, M += dM, X -= dX) {
     const uint64_t k = k0 + 2ull * i;
-    const uint64_t kl0 = uniform64(k);
-    if (kl0 >= kend) break;
-    const bool active = k < kend;
-    const uint64_t kk = active ? k : kl0;
-    const uint64_t M = a * kk + b;
-    const uint64_t X = dc - step * kk + 64ull * L - 32ull;
-    const int nb = bitlen64(dc - step * kl0 + 64ull * L - 32ull);
-    const uint32_t M32 = M == 1 ? 3u : (uint32_t)M;
+    if (uniform64(k) >= kend) break;
+    const int nb = bitlen64(uniform64(X));
+    const uint32_t M32 = (uint32_t)M;
     const uint32_t mp = neg_inv32(M32);
-    uint32_t x = mont_one32(M32);
+    uint32_t x;
+    if (kRunStart) {
+      x = 0u - q * M32;  // 2^32 - qM, below 2M
+      if (!kLazy) x = min(x, x - M32);
+    } else {
+      x = mont_one32(M32);
+    }
     const uint32_t xl = (uint32_t)X, xh = (uint32_t)(X >> 32);
-    for (int j = nb - 33; j >= 0; --j) x = sqr_redc32(x, (xh >> j) & 1u, M32, mp);
-    for (int j = (nb < 32 ? nb : 32) - 1; j >= 0; --j) x = sqr_redc32(x, (xl >> j) & 1u, M32, mp);
+    if (kLazy) {
+      for (int j = nb - 33; j >= 0; --j) x = sqr_redc32_lazy(x, (xh >> j) & 1u, M32, mp);
+      for (int j = (nb < 32 ? nb : 32) - 1; j >= 0; --j)
+        x = sqr_redc32_lazy(x, (xl >> j) & 1u, M32, mp);
+      x = min(x, x - M32);
+    } else {
+      for (int j = nb - 33; j >= 0; --j) x = sqr_redc32(x, (xh >> j) & 1u, M32, mp);
+      for (int j = (nb < 32 ? nb : 32) - 1; j >= 0; --j) x = sqr_redc32(x, (xl >> j) & 1u, M32, mp);
+    }
     uint64_t t[L];
     hensel32<L>(x, M32, mp, t);
     apply_masks<L>(t, msk);
-    if (active && M != 1) add_limbs<L>(sum, t);
+    if (k < kend && M != 1) add_limbs<L>(sum, t);
   }
 }
 
@@ -231,10 +251,12 @@ __device__ void head_chunks(const HeadSeg *segs, int nseg, uint64_t nchunks,
     uint64_t sum[L];
 #pragma unroll
     for (int i = 0; i < L; ++i) sum[i] = 0;
-    if (sg.cls == 64)
-      lane_run62<L>(k0, run, sg.pre, kend, sr.a, sr.b, dc, step, sg.P, sum);
-    else
-      lane_run32<L>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum);
+    switch (sg.cls) {
+      case 64: lane_run62<L>(k0, run, sg.pre, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+      case 31: lane_run32<L, false, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+      case 29: lane_run32<L, true, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+      default: lane_run32<L, true, false>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+    }
     if (neg) neg_limbs<L>(sum);
     wg_fold<L>(sum, red, sums, acc + sg.acc_off);
   }

@@ -8,7 +8,7 @@
 namespace pibbp {
 
 constexpr int PI_MAX_L = 17;          // ceil(PI_MAX_P / 64)
-constexpr int kMaxArgSegs = 21;       // 7 series x 3 modulus ranges
+constexpr int kMaxArgSegs = 35;       // 7 series x 5 modulus ranges
 
 // A range [kb, ke) of head indices (E >= 0) of series j of one query, all of
 // one modulus class; its chunks are numbered chunk0, chunk0 + 1, ...
@@ -18,7 +18,7 @@ struct HeadSeg {
   uint64_t d;          // n - 1
   uint32_t formula, j, P;
   uint32_t acc_off;    // the query's carry-save counters: acc + acc_off
-  uint32_t cls;        // 32: M < 2^31 (R = 2^32), 64: 2^31 <= M < 2^54 (R = 2^62)
+  uint32_t cls;        // R = 2^32: 22 (M < 2^22), 29 (< 2^29), 31 (< 2^31); 64: R = 2^62, M < 2^54
   uint32_t run;        // indices per lane per chunk; a chunk is 256 * run indices
   uint32_t pre;        // class 62: exponent bits taken into the ladder's start value
   uint32_t pad;

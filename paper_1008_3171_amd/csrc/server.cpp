@@ -110,9 +110,9 @@ int pi_server_create(uint32_t max_active, uint64_t step_terms, hipStream_t strea
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return PI_EDEVICE;
   // device bytes one slot can need: counters, result row and status, and its
-  // share of the step tables (up to 21 segments and one finalize record)
+  // share of the step tables (up to 35 segments and one finalize record)
   const size_t per_slot = kSlotCounters * 8u + PI_MAX_L * 8u + sizeof(pi_status) +
-                          21u * sizeof(HeadSeg) + sizeof(FinQuery);
+                          35u * sizeof(HeadSeg) + sizeof(FinQuery);
   const uint64_t by_mem = (uint64_t)(free_b / 4u / per_slot);
   const uint32_t cap = (uint32_t)std::min<uint64_t>(max_active, by_mem);
   if (cap == 0) return PI_ENOMEM;

@@ -66,3 +66,12 @@ def test_table_2_2_row_m13_checkpointed(tmp_path):
     S, code, N = checkpoint.finish(ck)
     assert code == pb.PI_OK
     assert S >> 64 == hex_bits(row[3], 256)
+
+
+def test_double_run_overlap():
+    from paper_1008_3171_amd import verify
+    row = [r for r in read_golden("table_2_2.txt") if r[0] == "11"][0]
+    bits, count, agree = verify.double_run(pb.BELLARD, int(row[1]) + 4, 256)
+    assert agree and count == 252
+    # the overlap starts at 10^11 + 5: bits 4.. of the printed row
+    assert bits == (hex_bits(row[3], 256) & ((1 << 252) - 1))
