@@ -30,6 +30,34 @@ PEAK_MUL32 = 256 * 64 * 2.4e9
 
 CLASS32_LIMIT = 2 ** 31
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "head_kernel_bellard_n1e12_P320_traffic.json")
+KERNEL_SOURCES = ["kernels.hip", "arith.h", "plan.h"]
+
+
+def kernel_source_hash():
+    """sha256 over the device sources of the head kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1008_3171_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the headline head kernel, from the rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs recorded in profiles/, each scaled by the
+    factor a plain 1 GiB copy gives the same counter; None when the kernel
+    sources changed after the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except OSError:
+        return None
+    if t.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return t["fetch_kib"] * 1024 * t["fetch_factor"] + t["write_kib"] * 1024 * t["write_factor"]
+
 
 def series(formula):
     # (c, a, b) per series and the step; the sign does not change the work
@@ -345,7 +373,8 @@ def main():
         "nterms": N,
         "result_hex": "%0*x" % ((w + 3) // 4, S >> (P - w)),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_MUL32 / 1e12,
-                     "unit": "Tmul32/s", "frac": achieved / PEAK_MUL32, "traffic": None,
+                     "unit": "Tmul32/s", "frac": achieved / PEAK_MUL32,
+                     "traffic": measured_traffic() if (n, w, P, formula) == (10 ** 12, 256, 320, pb.BELLARD) else None,
                      "mul32_per_launch": mul32},
     }
     if n == 10 ** 12 and w == 256 and formula == pb.BELLARD:

@@ -73,15 +73,21 @@ __device__ __forceinline__ void head_term32(uint64_t E, uint32_t M, uint32_t P, 
 
 // ---- carry-save workgroup reduction -----------------------------------------
 
-// Adds the 256 lane values v (L limbs each, mod 2^(64L)) into 2L 64-bit
-// counters in carry-save form. The lane values are first summed exactly:
-// thread h adds up the 32-bit halves h of all lanes (below 2^40), then thread
-// 0 propagates the carries, so each counter receives one value below 2^32 per
-// call. The counters are exact while fewer than 2^32 calls add into them.
+constexpr uint32_t kNoQuery = 0xffffffffu;
+
+// Adds the 256 lane values v (L limbs each, mod 2^(64L)) to the workgroup's
+// pending column sums. The lane values are first summed exactly: thread h adds
+// up the 32-bit halves h of all lanes (below 2^40), then thread 0 propagates
+// the carries, so each call adds one value below 2^32 to each pending column.
+// Pending columns belong to one query (counters at acc + pend_off); a chunk of
+// another query first flushes them into that query's carry-save counters with
+// 2L atomics. The counters stay exact while fewer than 2^32 chunks of one
+// query are added up, which the host guarantees.
 template <int L>
 __device__ __forceinline__ void wg_fold(const uint64_t (&v)[L], uint32_t (*red)[256],
-                                        unsigned long long *sums,
-                                        unsigned long long *counters) {
+                                        unsigned long long *sums, unsigned long long *pend,
+                                        uint32_t *pend_off, uint32_t acc_off,
+                                        unsigned long long *acc) {
   const uint32_t tid = threadIdx.x;
 #pragma unroll
   for (int i = 0; i < L; ++i) {
@@ -104,8 +110,26 @@ __device__ __forceinline__ void wg_fold(const uint64_t (&v)[L], uint32_t (*red)[
     }
   }
   __syncthreads();
-  if (tid < 2u * L && sums[tid]) atomicAdd(&counters[tid], sums[tid]);
+  if (tid < 2u * L) {
+    const uint32_t cur = *pend_off;
+    if (cur != acc_off) {
+      if (cur != kNoQuery && pend[tid]) atomicAdd(&acc[(uint64_t)cur + tid], pend[tid]);
+      pend[tid] = 0;
+    }
+    pend[tid] += sums[tid];
+  }
   __syncthreads();
+  if (tid == 0) *pend_off = acc_off;
+  __syncthreads();
+}
+
+// The workgroup's last flush of its pending column sums.
+template <int L>
+__device__ __forceinline__ void wg_flush(const unsigned long long *pend, const uint32_t *pend_off,
+                                         unsigned long long *acc) {
+  const uint32_t tid = threadIdx.x;
+  if (tid < 2u * L && *pend_off != kNoQuery && pend[tid])
+    atomicAdd(&acc[(uint64_t)*pend_off + tid], pend[tid]);
 }
 
 // ---- the head kernel ---------------------------------------------------------
@@ -233,9 +257,13 @@ template <int L>
 __device__ void head_chunks(const HeadSeg *segs, int nseg, uint64_t nchunks,
                             unsigned long long *acc) {
   __shared__ uint32_t red[2 * L][256];
-  __shared__ unsigned long long sums[2 * L];
+  __shared__ unsigned long long sums[2 * L], pend[2 * L];
+  __shared__ uint32_t pend_off;
   const uint32_t tid = threadIdx.x;
   const uint32_t pair = tid >> 1, par = tid & 1u;
+  if (tid < 2u * L) pend[tid] = 0;
+  if (tid == 0) pend_off = kNoQuery;
+  __syncthreads();
   for (uint64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
     const HeadSeg sg = find_seg(segs, nseg, ch);
     const uint32_t run = sg.run;
@@ -258,8 +286,9 @@ __device__ void head_chunks(const HeadSeg *segs, int nseg, uint64_t nchunks,
       default: lane_run32<L, true, false>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
     }
     if (neg) neg_limbs<L>(sum);
-    wg_fold<L>(sum, red, sums, acc + sg.acc_off);
+    wg_fold<L>(sum, red, sums, pend, &pend_off, sg.acc_off, acc);
   }
+  wg_flush<L>(pend, &pend_off, acc);
 }
 
 template <int L>
