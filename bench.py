@@ -203,11 +203,29 @@ def batch_vs_loop(pb, torch, count=4096, seed=1008):
     tb, wb = timed(batch)
     tl, wl = timed(loop)
     same = bool(torch.equal(out_b, out_l) and torch.equal(st_b, st_l))
+    # the same batch as a plan captured once into a HIP graph, then replayed
+    out_g = torch.zeros(total, dtype=torch.int64, device="cuda")
+    st_g = torch.zeros(4 * count, dtype=torch.int32, device="cuda")
+    plan = pb.BatchPlan(qarr, count, out_g, st_g)
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        plan.launch(stream=side)
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.launch(stream=torch.cuda.current_stream())
+    graph.replay()
+    tg, wg = timed(graph.replay)
+    same_graph = bool(torch.equal(out_b, out_g) and torch.equal(st_b, st_g))
+    plan.close()
     certified = all(pb.status_of(st_b, i)[0] == pb.PI_OK for i in range(count))
     print("batch vs loop done", file=sys.stderr, flush=True)
     return {"queries": count, "head_terms": terms, "batch_s": tb, "loop_s": tl,
             "batch_queries_per_s": count / tb, "loop_queries_per_s": count / tl,
             "speedup": tl / tb, "batch_terms_per_s": terms / tb,
+            "graph_replay_s": tg, "graph_speedup": tl / tg, "graph_identical": same_graph,
             "batch_wall_s": wb, "loop_wall_s": wl, "identical_outputs": same,
             "all_certified": certified,
             "workload": "Bellard, n = floor(10^U), U ~ U(4, 9), w in {32,64,128,256}, "

@@ -143,6 +143,20 @@ typedef struct {
 PI_API int pi_extract_batch(const pi_query *q, int count, uint64_t *out, pi_status *status,
                      void *workspace, size_t ws_bytes, hipStream_t stream);
 
+/* A planned batch that can be launched many times, e.g. captured once into a
+ * HIP graph and replayed. pi_batch_create plans the queries, allocates the
+ * plan's own device memory and uploads its tables (synchronously);
+ * pi_batch_launch then only enqueues kernels on `stream` (clear the counters,
+ * one head launch per limb class, one finalize launch per class): it never
+ * allocates, copies from the host or waits, so it can be captured. Every
+ * launch writes the results again into the out/status given at creation.
+ * Launches of one plan must not overlap (they share its counters). */
+typedef struct pi_batch pi_batch;
+PI_API int pi_batch_create(const pi_query *q, int count, uint64_t *out, pi_status *status,
+                           pi_batch **plan);
+PI_API int pi_batch_launch(pi_batch *plan, hipStream_t stream);
+PI_API void pi_batch_destroy(pi_batch *plan);
+
 /* Bytes of device workspace pi_extract_batch needs for these queries. */
 PI_API size_t pi_workspace_size(const pi_query *q, int count);
 

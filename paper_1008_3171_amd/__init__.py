@@ -316,3 +316,41 @@ def combine(parts, count: int, P: int, nbits: int, nseries: int, nterms: int, ou
     if rc != 0:
         raise PiError(rc, "pi_combine")
     return out, status
+
+
+class BatchPlan:
+    """pi_batch_*: a batch planned once and launched many times (capturable)."""
+
+    def __init__(self, qarr, count: int, out, status=None):
+        lib = load()
+        vp = ctypes.c_void_p
+        lib.pi_batch_create.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.POINTER(vp)]
+        lib.pi_batch_create.restype = ctypes.c_int
+        lib.pi_batch_launch.argtypes = [vp, vp]
+        lib.pi_batch_launch.restype = ctypes.c_int
+        lib.pi_batch_destroy.argtypes = [vp]
+        self._lib = lib
+        self.out, self.status = out, status
+        h = vp()
+        rc = lib.pi_batch_create(ctypes.cast(qarr, vp), count, vp(out.data_ptr()),
+                                 vp(status.data_ptr() if status is not None else None),
+                                 ctypes.byref(h))
+        if rc != 0:
+            raise PiError(rc, "pi_batch_create")
+        self._h = h
+
+    def launch(self, stream=None):
+        rc = self._lib.pi_batch_launch(self._h, _stream(stream))
+        if rc != 0:
+            raise PiError(rc, "pi_batch_launch")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.pi_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -402,6 +402,9 @@ int plan_batch(const pi_query *q, int count, BatchPlan *bp) {
   return PI_OK;
 }
 
+int launch_planned(const BatchPlan &bp, char *ws, uint64_t *out, pi_status *status, int grid_max,
+                   hipStream_t st);
+
 // Upload the tables (through pinned staging), clear the counters, then one
 // head launch and one finalize launch per limb class, all on `st`.
 int run_batch(BatchPlan &bp, char *ws, uint64_t *out, pi_status *status, hipStream_t st) {
@@ -430,22 +433,7 @@ int run_batch(BatchPlan &bp, char *ws, uint64_t *out, pi_status *status, hipStre
   }
   if (hipEventRecord(sg->done, st) != hipSuccess) return PI_EDEVICE;
   sg->pending = true;
-  for (const ClassPlan &c : bp.cls) {
-    auto *acc = (unsigned long long *)(ws + c.acc_off);
-    auto *segs = (HeadSeg *)(ws + c.seg_off);
-    auto *fins = (FinQuery *)(ws + c.fin_off);
-    if (int e = hip_err(launch_zero(acc, c.fins.size() * 2u * (uint64_t)c.Lk, st))) return e;
-    if (c.nchunks) {
-      const int grid = (int)std::min<uint64_t>(c.nchunks, (uint64_t)grid_max);
-      if (int e = hip_err(launch_head_ptr(c.Lk, segs, (int)c.segs.size(), c.nchunks, grid, acc, st)))
-        return e;
-    }
-    FinQuery none;
-    memset(&none, 0, sizeof none);
-    if (int e = hip_err(launch_finalize(c.Lk, none, fins, (int)c.fins.size(), acc, out, status, st)))
-      return e;
-  }
-  return PI_OK;
+  return launch_planned(bp, ws, out, status, grid_max, st);
 }
 
 }  // namespace host
@@ -504,6 +492,88 @@ uint64_t pi_head_terms(int formula, uint64_t n) {
   for (int j = 0; j < kHJ[formula]; ++j)
     tot += first_tail(kHSeries[formula][j], kHStep[formula], n - 1);
   return tot;
+}
+
+}  // extern "C"
+
+struct pi_batch {
+  BatchPlan bp;
+  char *ws = nullptr;
+  uint64_t *out = nullptr;
+  pi_status *status = nullptr;
+  int grid_max = 2048;
+};
+
+namespace pibbp {
+namespace host {
+// Kernel launches of a planned batch whose tables are already on the device.
+int launch_planned(const BatchPlan &bp, char *ws, uint64_t *out, pi_status *status, int grid_max,
+                   hipStream_t st) {
+  for (const ClassPlan &c : bp.cls) {
+    auto *acc = (unsigned long long *)(ws + c.acc_off);
+    auto *segs = (HeadSeg *)(ws + c.seg_off);
+    auto *fins = (FinQuery *)(ws + c.fin_off);
+    if (int e = hip_err(launch_zero(acc, c.fins.size() * 2u * (uint64_t)c.Lk, st))) return e;
+    if (c.nchunks) {
+      const int grid = (int)std::min<uint64_t>(c.nchunks, (uint64_t)grid_max);
+      if (int e = hip_err(launch_head_ptr(c.Lk, segs, (int)c.segs.size(), c.nchunks, grid, acc, st)))
+        return e;
+    }
+    FinQuery none;
+    memset(&none, 0, sizeof none);
+    if (int e = hip_err(launch_finalize(c.Lk, none, fins, (int)c.fins.size(), acc, out, status, st)))
+      return e;
+  }
+  return PI_OK;
+}
+}  // namespace host
+}  // namespace pibbp
+
+extern "C" {
+
+int pi_batch_create(const pi_query *q, int count, uint64_t *out, pi_status *status,
+                    pi_batch **plan) {
+  if (!plan || count <= 0 || !q || !out) return PI_EINVAL;
+  *plan = nullptr;
+  pi_batch *b = new pi_batch();
+  if (int e = plan_batch(q, count, &b->bp)) {
+    delete b;
+    return e;
+  }
+  for (ClassPlan &c : b->bp.cls)
+    for (FinQuery &f : c.fins) f.want_status = status != nullptr ? 1u : 0u;
+  if (hipMalloc((void **)&b->ws, b->bp.bytes) != hipSuccess) {
+    delete b;
+    return PI_ENOMEM;
+  }
+  for (const ClassPlan &c : b->bp.cls) {
+    if ((!c.segs.empty() && hipMemcpy(b->ws + c.seg_off, c.segs.data(),
+                                      c.segs.size() * sizeof(HeadSeg),
+                                      hipMemcpyHostToDevice) != hipSuccess) ||
+        hipMemcpy(b->ws + c.fin_off, c.fins.data(), c.fins.size() * sizeof(FinQuery),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(b->ws);
+      delete b;
+      return PI_EDEVICE;
+    }
+  }
+  b->out = out;
+  b->status = status;
+  b->grid_max = resident_grid();
+  *plan = b;
+  return PI_OK;
+}
+
+int pi_batch_launch(pi_batch *plan, hipStream_t stream) {
+  if (!plan) return PI_EINVAL;
+  return launch_planned(plan->bp, plan->ws, plan->out, plan->status, plan->grid_max, stream);
+}
+
+void pi_batch_destroy(pi_batch *plan) {
+  if (!plan) return;
+  (void)hipDeviceSynchronize();
+  (void)hipFree(plan->ws);
+  delete plan;
 }
 
 size_t pi_workspace_size(const pi_query *q, int count) {

@@ -90,3 +90,46 @@ def test_empty_and_invalid_batches():
     out = torch.zeros(total, dtype=torch.int64, device="cuda")
     with pytest.raises(pb.PiError):
         pb.extract_batch(qarr, 2, out)
+
+
+def test_planned_batch_eager_and_graph_replays():
+    # a batch plan launched eagerly equals pi_extract_batch; captured into a
+    # HIP graph, every replay (with eager work in between) gives it again
+    specs = workloads.batch_queries(256, seed=11, hi_exp=7)
+    qarr, total = pb.make_queries(specs)
+    ref = run_batch(specs)
+    out = torch.zeros(total, dtype=torch.int64, device="cuda")
+    status = torch.zeros(4 * len(specs), dtype=torch.int32, device="cuda")
+    plan = pb.BatchPlan(qarr, len(specs), out, status)
+
+    def results():
+        vals = [int(v) & 0xFFFFFFFFFFFFFFFF for v in out.cpu().tolist()]
+        res = []
+        for i, (f, n, w, P) in enumerate(specs):
+            L, off = pb.limbs(P), qarr[i].out_offset
+            S = sum(vals[off + j] << (64 * j) for j in range(L)) >> (64 * L - P)
+            code, N = pb.status_of(status, i)
+            res.append((S, N, code == pb.PI_OK))
+        return res
+
+    plan.launch()
+    torch.cuda.synchronize()
+    assert results() == ref
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.launch(stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.launch(stream=torch.cuda.current_stream())
+    for rep in range(3):
+        out.zero_()
+        status.zero_()
+        single(pb.BELLARD, 10 ** 6 + rep, 64, 96)      # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert results() == ref, rep
+    plan.close()
