@@ -8,8 +8,8 @@ reduction and the certification. Inputs are the query parameters
 themselves; nothing is read from disk.
 
 Prints one JSON line. `value` = head terms per second of the timed steps.
-`roofline` prices the head kernel against the chip's 32-bit multiply issue
-rate; `cpu_baseline` is the oracle on a bounded seeded sub-slice of the same
+`roofline` prices the head kernel's data-path instructions against the
+chip's VALU issue rate; `cpu_baseline` is the oracle on a bounded seeded sub-slice of the same
 workload.
 """
 from __future__ import annotations
@@ -24,11 +24,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz: v_mad_u64_u32 (a 32x32->64
-# multiply-add) issues at the full VALU rate on gfx950.
-PEAK_MUL32 = 256 * 64 * 2.4e9
-
-CLASS32_LIMIT = 2 ** 31
+# 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz: the VALU issue rate.
+# v_fma_f64 (78.6 TFLOP/s = this rate x 2 flops) and v_mad_u64_u32 both issue
+# at it on gfx950, so the head kernel is priced in VALU lane-operations.
+PEAK_VALU = 256 * 64 * 2.4e9
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "head_kernel_bellard_n1e12_P320_traffic.json")
 KERNEL_SOURCES = ["kernels.hip", "arith.h", "plan.h"]
@@ -83,18 +82,36 @@ def _pre_bits(run, Mmin, Mmax, a):
     return 0
 
 
-def mul32_per_launch(formula, n, P, run=64):
-    """Algorithmic 32-bit multiplies of every head term of one extraction.
+# VALU instructions of the head kernel's data path, from the compiled gfx950
+# code (loop control and scheduling excluded): per exponent bit of the ladder,
+# and per term for everything else (start value, reciprocal or -M^-1, the
+# residue, the L-limb Hensel division at L = 5, masks and the accumulation).
+#   class: (first modulus, per bit, per term, X offset - 64L)
+KERNEL_CLASSES = [
+    ("22", 0, 5, 77, -32),         # R = 2^32, lazy, start by doublings
+    ("29", 2 ** 22, 5, 71, -32),   # R = 2^32, lazy, run-quotient start
+    ("31", 2 ** 29, 7, 71, -32),   # R = 2^32, reduced residues
+    ("f2", 2 ** 31, 7, 99, 0),    # binary64, two-bit windows
+    ("f1", 2 ** 46, 8, 101, 0),    # binary64, one-bit windows
+    ("62", 2 ** 48, 16, 116, -62), # R = 2^62, two 31-bit digits
+]
 
-    Class 62 (2^31 <= M, R = 2^62, two 31-bit digits): bitlen(X) - pre
-    Montgomery squarings, X = E + 64L - 62, where `pre` top exponent bits
-    (0..3, per modulus range) go into the start value; 9 multiplies per
-    squaring (3 for the square, 2 reduction digits, 4 digit-by-modulus
-    products); 12 for -M^-1 mod 2^64; 2 for the start value 2^62 - qM; 7 per
-    limb of the Hensel division (3 for the low product, 4 for the high half of
-    t M). Class 32 (M < 2^31, R = 2^32): 3 per squaring (X = E + 64L - 32),
-    6 for the inverse, 4 per 64-bit limb of the division.
-    """
+
+def _start_bits(cls, nb, pre):
+    if cls == "f2":
+        return nb if nb <= 6 else 6 - ((nb - 6) & 1)
+    if cls == "f1":
+        return min(nb, 6)
+    if cls == "62":
+        return min(pre, nb)
+    return 0
+
+
+def valu_ops_per_launch(formula, n, P, run=64):
+    """Data-path VALU instructions of every head term of one extraction:
+    per term, (ladder bits) x (per bit) + (per term) for the term's modulus
+    class, with the ladder running over X = E + 64L + offset minus the start
+    bits. Returns (ops, head terms)."""
     rows, step = series(formula)
     L = (P + 63) // 64
     d = n - 1
@@ -108,27 +125,24 @@ def mul32_per_launch(formula, n, P, run=64):
         def first_k(mlim):
             return min(K, max(0, -(-(mlim - b) // a)))
 
-        ks, k36 = first_k(CLASS32_LIMIT), first_k(2 ** 36)
-        for lo, hi, cls in ((0, ks, 32), (ks, k36, 62), (k36, K, 62)):
+        bounds = [first_k(m) for _, m, _, _, _ in KERNEL_CLASSES] + [K]
+        for i, (cls, _, per_bit, fixed, off) in enumerate(KERNEL_CLASSES):
+            lo, hi = bounds[i], bounds[i + 1]
             if lo >= hi:
                 continue
-            off = 64 * L - 62 if cls == 62 else 64 * L - 32
-            if cls == 62:
+            pre = 0
+            if cls == "62":
                 pre = _pre_bits(min(run, max(1, (hi - lo) // 1024)), a * lo + b,
                                 a * (hi - 1) + b, a)
-                per_sq, fixed = 9, 14 + 7 * L - 9 * pre
-            else:
-                per_sq, fixed = 3, 6 + 4 * L
-            # X(k) = d + c - step k + off decreases with k; sum bitlen over bands
+            base = d + c + 64 * L + off
             k = lo
             while k < hi:
-                X = d + c - step * k + off
+                X = base - step * k
                 bl = X.bit_length()
                 lowX = 1 << (bl - 1) if bl > 0 else 0
-                # last k with X(k) >= lowX
-                kmax = min(hi - 1, (d + c + off - lowX) // step) if bl > 0 else hi - 1
+                kmax = min(hi - 1, (base - lowX) // step) if bl > 0 else hi - 1
                 cnt = kmax - k + 1
-                total += cnt * (bl * per_sq + fixed)
+                total += cnt * ((bl - _start_bits(cls, bl, pre)) * per_bit + fixed)
                 terms += cnt
                 k = kmax + 1
     return total, terms
@@ -366,10 +380,10 @@ def main():
     S = pb.to_int(out, P)
     print("timed steps done", file=sys.stderr, flush=True)
 
-    mul32, terms = mul32_per_launch(formula, n, P)
+    ops, terms = valu_ops_per_launch(formula, n, P)
     assert terms == pb.head_terms(formula, n)
     value = terms / (ms * 1e-3)
-    achieved = mul32 / (ms * 1e-3)
+    achieved = ops / (ms * 1e-3)
     rec = {
         "metric": "modexp terms/s at n=1e12, 256-bit exact",
         "value": value,
@@ -390,10 +404,10 @@ def main():
         "certified": code == pb.PI_OK,
         "nterms": N,
         "result_hex": "%0*x" % ((w + 3) // 4, S >> (P - w)),
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_MUL32 / 1e12,
-                     "unit": "Tmul32/s", "frac": achieved / PEAK_MUL32,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU / 1e12,
+                     "unit": "T VALU lane-ops/s", "frac": achieved / PEAK_VALU,
                      "traffic": measured_traffic() if (n, w, P, formula) == (10 ** 12, 256, 320, pb.BELLARD) else None,
-                     "mul32_per_launch": mul32},
+                     "valu_ops_per_launch": ops},
     }
     if n == 10 ** 12 and w == 256 and formula == pb.BELLARD:
         # Table 2.2, m = 12 starts at 10^12 + 1: our bits 1..255

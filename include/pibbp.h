@@ -164,6 +164,14 @@ PI_API size_t pi_workspace_size(const pi_query *q, int count);
  * floor((n-1+c_j)/step)+1 where that is positive. Host-only arithmetic. */
 PI_API uint64_t pi_head_terms(int formula, uint64_t n);
 
+/* Launch shape of the head kernel instance for `limbs` = ceil(P/64) rounded
+ * up to an instantiated count (1-6, 8, 12, 17), or every instance when limbs
+ * is 0: wg_per_cu workgroups per CU (0: as many as fit, from the occupancy
+ * API) and run_cap, the most indices one lane takes per chunk. Results do not
+ * depend on these; only speed does. The autotuner sets them from its cache. */
+PI_API int pi_set_tuning(int limbs, uint32_t wg_per_cu, uint32_t run_cap);
+PI_API int pi_get_tuning(int limbs, uint32_t *wg_per_cu, uint32_t *run_cap);
+
 /* Static text for a return code. */
 PI_API const char *pi_strerror(int code);
 

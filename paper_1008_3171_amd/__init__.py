@@ -64,8 +64,45 @@ def load():
         lib.pi_shutdown.argtypes = []
         for f in (lib.pi_extract, lib.pi_extract_ex, lib.pi_sum_slice, lib.pi_extract_batch):
             f.restype = i32
+        lib.pi_set_tuning.argtypes = [i32, u32, u32]
+        lib.pi_set_tuning.restype = i32
+        lib.pi_get_tuning.argtypes = [i32, ctypes.POINTER(u32), ctypes.POINTER(u32)]
+        lib.pi_get_tuning.restype = i32
         _lib = lib
+        _apply_tuning_cache()
     return _lib
+
+
+def tuning_cache_path() -> str:
+    """Where the autotuner keeps its choices (PIBBP_TUNING overrides)."""
+    return os.environ.get("PIBBP_TUNING") or os.path.join(
+        os.path.expanduser("~"), ".cache", "pibbp", "tuning.json")
+
+
+def _apply_tuning_cache():
+    import json
+    path = tuning_cache_path()
+    try:
+        with open(path) as f:
+            cache = json.load(f)
+    except (OSError, ValueError):
+        return
+    for limbs_s, t in cache.get("classes", {}).items():
+        _lib.pi_set_tuning(int(limbs_s), int(t["wg_per_cu"]), int(t["run_cap"]))
+
+
+def set_tuning(limbs: int, wg_per_cu: int, run_cap: int):
+    rc = load().pi_set_tuning(limbs, wg_per_cu, run_cap)
+    if rc != 0:
+        raise PiError(rc, "pi_set_tuning")
+
+
+def get_tuning(limbs: int):
+    a, b = ctypes.c_uint32(), ctypes.c_uint32()
+    rc = load().pi_get_tuning(limbs, ctypes.byref(a), ctypes.byref(b))
+    if rc != 0:
+        raise PiError(rc, "pi_get_tuning")
+    return a.value, b.value
 
 
 def _torch():

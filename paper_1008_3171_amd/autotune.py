@@ -1,0 +1,90 @@
+"""Autotuner for the head kernel's launch shape.
+
+For each kernel limb class it times a representative extraction under every
+candidate (workgroups per CU, run cap) and keeps the fastest; the results
+are the same whatever the shape, so only speed is compared (and checked
+equal). Choices are cached as JSON (paper_1008_3171_amd.tuning_cache_path())
+and applied by the binding when the library is loaded.
+
+    python -m paper_1008_3171_amd.autotune [--out FILE]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+
+# limb class -> (formula, n, nbits, P): a query of that class with enough
+# work (tenths of a second) that launch cost does not decide
+WORKLOADS = {
+    2: (1, 10 ** 10, 64, 128),
+    3: (1, 10 ** 10, 128, 192),
+    5: (1, 10 ** 11, 256, 320),
+}
+WG_PER_CU = (0, 2, 3, 4, 5, 6, 8, 12, 16)
+RUN_CAPS = (32, 64, 128)
+
+
+def time_one(pb, torch, spec, reps=2):
+    f, n, w, P = spec
+    out = torch.zeros(pb.limbs(P), dtype=torch.int64, device="cuda")
+    st = torch.zeros(4, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    best = None
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        pb.extract(f, n, w, P, out=out, status=st, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    return best, pb.to_int(out)
+
+
+def tune(classes=None, log=sys.stdout):
+    import torch
+    import paper_1008_3171_amd as pb
+    classes = sorted(classes or WORKLOADS)
+    arch = torch.cuda.get_device_properties(0).gcnArchName
+    result = {"arch": arch, "classes": {}}
+    for L in classes:
+        spec = WORKLOADS[L]
+        pb.set_tuning(L, 0, 64)
+        base_ms, ref = time_one(pb, torch, spec)
+        best = (base_ms, 0, 64)
+        for wg in WG_PER_CU:
+            for cap in RUN_CAPS:
+                pb.set_tuning(L, wg, cap)
+                ms, val = time_one(pb, torch, spec)
+                if val != ref:
+                    raise RuntimeError("launch shape changed the result: %r" % ((L, wg, cap),))
+                print(json.dumps({"limbs": L, "wg_per_cu": wg, "run_cap": cap, "ms": ms}),
+                      file=log, flush=True)
+                if ms < best[0]:
+                    best = (ms, wg, cap)
+        pb.set_tuning(L, best[1], best[2])
+        result["classes"][str(L)] = {"wg_per_cu": best[1], "run_cap": best[2], "ms": best[0],
+                                     "default_ms": base_ms, "workload": list(spec)}
+    return result
+
+
+def main(argv=None):
+    import paper_1008_3171_amd as pb
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--out", default=None, help="cache file (default: the binding's)")
+    args = ap.parse_args(argv)
+    res = tune()
+    path = args.out or pb.tuning_cache_path()
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -83,7 +83,9 @@ int make_plan(int formula, uint64_t n, uint32_t w, uint32_t P, uint32_t jmask, u
     qp->hk1[j] = std::min(k1, kt);
     qp->tk0[j] = std::min(std::max(k0, kt), kz);
     qp->tk1[j] = std::max(qp->tk0[j], std::min(k1, kz));
-    const uint64_t hi = std::max(qp->hk1[j], qp->tk1[j]);
+    // largest index whose modulus is used: ends of the non-empty ranges only
+    const uint64_t hi = std::max(qp->hk1[j] > qp->hk0[j] ? qp->hk1[j] : 0,
+                                 qp->tk1[j] > qp->tk0[j] ? qp->tk1[j] : 0);
     if (hi > 0 && (hi - 1) > (kModulusLimit - s.b) / s.a) return PI_EUNSUPPORTED;
     qp->nhead += qp->hk1[j] - qp->hk0[j];
   }
@@ -92,12 +94,11 @@ int make_plan(int formula, uint64_t n, uint32_t w, uint32_t P, uint32_t jmask, u
 
 // Head segments of a plan, split by modulus range: below 2^22 (R = 2^32,
 // Montgomery one by doublings), [2^22, 2^29) (R = 2^32, lazy residues),
-// [2^29, 2^31) (R = 2^32), [2^31, 2^36) and from 2^36 (R = 2^62; split so
-// that the small moduli, where a lane run's starting value has the most slack
-// to cover, do not limit the run length and start bits of the rest).
+// [2^29, 2^31) (R = 2^32), [2^31, 2^46) (binary64, two-bit windows),
+// [2^46, 2^48) (binary64, one-bit windows) and from 2^48 (R = 2^62).
 void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &out) {
-  static const uint64_t kLim[4] = {1ull << 22, 1ull << 29, kClass32Limit, 1ull << 36};
-  static const uint32_t kCls[5] = {22, 29, 31, 64, 64};
+  static const uint64_t kLim[5] = {1ull << 22, 1ull << 29, kClass32Limit, 1ull << 46, 1ull << 48};
+  static const uint32_t kCls[6] = {22, 29, 31, 46, 48, 64};
   for (int j = 0; j < kHJ[qp.formula]; ++j) {
     const HostSeries &s = kHSeries[qp.formula][j];
     const uint64_t kb = qp.hk0[j], ke = qp.hk1[j];
@@ -106,8 +107,8 @@ void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &
       const uint64_t k = Mlim > s.b ? (Mlim - s.b + s.a - 1) / s.a : 0;
       return std::min(std::max(k, kb), ke);
     };
-    const uint64_t cuts[6] = {kb, first_k(kLim[0]), first_k(kLim[1]), first_k(kLim[2]),
-                              first_k(kLim[3]), ke};
+    const uint64_t cuts[7] = {kb,           first_k(kLim[0]), first_k(kLim[1]), first_k(kLim[2]),
+                              first_k(kLim[3]), first_k(kLim[4]), ke};
     HeadSeg g;
     memset(&g, 0, sizeof g);
     g.d = qp.d;
@@ -115,7 +116,7 @@ void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &
     g.j = (uint32_t)j;
     g.P = qp.P;
     g.acc_off = acc_off;
-    for (int c = 0; c < 5; ++c) {
+    for (int c = 0; c < 6; ++c) {
       if (cuts[c] >= cuts[c + 1]) continue;
       g.kb = cuts[c];
       g.ke = cuts[c + 1];
@@ -243,19 +244,57 @@ void *arena(hipStream_t st, size_t bytes, int *err) {
   return a.dev;
 }
 
+// Launch shape per kernel limb class: workgroups per CU (0: as many as fit,
+// from the occupancy API) and the cap on indices per lane per chunk. Set by
+// pi_set_tuning (e.g. from the autotuner's cache).
+struct Tuning {
+  uint32_t wg_per_cu = 0;
+  uint32_t run_cap = 64;
+};
+Tuning g_tune[PI_MAX_L + 1];
+std::map<std::pair<int, int>, int> g_occ;  // (device, Lk) -> resident workgroups per CU
+
 // Chunk length per lane: long runs amortize the per-chunk fold, but a small
 // query still has to fill every workgroup slot several times over. A query's
 // carry-save counters take one value below 2^32 per chunk, so its chunk count
 // must stay below 2^31: very large queries get longer runs.
-uint32_t pick_run(uint64_t head_terms, int grid) {
+uint32_t pick_run(uint64_t head_terms, int grid, uint32_t cap) {
   const uint64_t per = head_terms / (256ull * (uint64_t)grid * 4ull);
   const uint64_t floor_run = head_terms / (256ull << 31) + 1u;
-  return (uint32_t)std::max<uint64_t>(floor_run, std::min<uint64_t>(64, std::max<uint64_t>(1, per)));
+  return (uint32_t)std::max<uint64_t>(floor_run, std::min<uint64_t>(cap, std::max<uint64_t>(1, per)));
 }
 
-int resident_grid() {
+uint32_t run_cap_for(int Lk) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_tune[Lk].run_cap;
+}
+
+// Grid of a head launch for limb class Lk: CUs x workgroups per CU.
+int resident_grid(int Lk) {
   const int cus = device_cus();
-  return cus > 0 ? cus * 8 : 2048;
+  if (cus <= 0) return 2048;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  uint32_t per = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    per = g_tune[Lk].wg_per_cu;
+  }
+  if (per == 0) {
+    int occ = 0;
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      auto it = g_occ.find({dev, Lk});
+      if (it != g_occ.end()) occ = it->second;
+    }
+    if (occ == 0) {
+      occ = std::max(1, head_occupancy(Lk));
+      std::lock_guard<std::mutex> lk(g_mu);
+      g_occ[{dev, Lk}] = occ;
+    }
+    per = (uint32_t)occ;
+  }
+  return cus * (int)per;
 }
 
 int hip_err(hipError_t e) { return e == hipSuccess ? PI_OK : PI_EDEVICE; }
@@ -328,8 +367,9 @@ int run_single(const QueryPlan &qp, uint64_t *out, pi_status *status, uint32_t m
                hipStream_t st) {
   std::vector<HeadSeg> segs;
   head_segments(qp, 0, segs);
-  const int grid_max = resident_grid();
-  const uint64_t nchunks = number_chunks(segs, pick_run(qp.nhead, grid_max), 0);
+  const int grid_max = resident_grid(qp.Lk);
+  const uint64_t nchunks =
+      number_chunks(segs, pick_run(qp.nhead, grid_max, run_cap_for(qp.Lk)), 0);
   HeadSegTable tab;
   memset(&tab, 0, sizeof tab);
   for (size_t i = 0; i < segs.size(); ++i) tab.s[i] = segs[i];
@@ -353,6 +393,7 @@ int run_single(const QueryPlan &qp, uint64_t *out, pi_status *status, uint32_t m
 // records, and where each lives in the workspace.
 struct ClassPlan {
   int Lk = 0;
+  int grid = 2048;  // head launch grid, fixed at planning
   std::vector<HeadSeg> segs;
   std::vector<FinQuery> fins;
   uint64_t nchunks = 0;
@@ -368,7 +409,6 @@ size_t align256(size_t x) { return (x + 255u) & ~(size_t)255u; }
 int plan_batch(const pi_query *q, int count, BatchPlan *bp) {
   if (count < 0 || (count > 0 && !q)) return PI_EINVAL;
   std::map<int, int> by_class;  // Lk -> index in bp->cls
-  const int grid_max = 2048;
   for (int i = 0; i < count; ++i) {
     if (q[i].reserved != 0) return PI_EINVAL;
     QueryPlan qp;
@@ -379,12 +419,14 @@ int plan_batch(const pi_query *q, int count, BatchPlan *bp) {
       it = by_class.emplace(qp.Lk, (int)bp->cls.size()).first;
       bp->cls.emplace_back();
       bp->cls.back().Lk = qp.Lk;
+      bp->cls.back().grid = resident_grid(qp.Lk);
     }
     ClassPlan &c = bp->cls[it->second];
     const uint32_t local = (uint32_t)c.fins.size();
     std::vector<HeadSeg> segs;
     head_segments(qp, local * 2u * (uint32_t)qp.Lk, segs);
-    const uint32_t cap = std::max(pick_run(qp.nhead, grid_max), min_run_cap(qp.nhead));
+    const uint32_t cap = std::max(pick_run(qp.nhead, resident_grid(qp.Lk), run_cap_for(qp.Lk)),
+                                  min_run_cap(qp.nhead));
     c.nchunks += number_chunks(segs, cap, c.nchunks);
     c.segs.insert(c.segs.end(), segs.begin(), segs.end());
     c.fins.push_back(fin_query(qp, q[i].out_offset, 1u, (uint32_t)i, local * 2u * (uint32_t)qp.Lk));
@@ -402,13 +444,12 @@ int plan_batch(const pi_query *q, int count, BatchPlan *bp) {
   return PI_OK;
 }
 
-int launch_planned(const BatchPlan &bp, char *ws, uint64_t *out, pi_status *status, int grid_max,
+int launch_planned(const BatchPlan &bp, char *ws, uint64_t *out, pi_status *status,
                    hipStream_t st);
 
 // Upload the tables (through pinned staging), clear the counters, then one
 // head launch and one finalize launch per limb class, all on `st`.
 int run_batch(BatchPlan &bp, char *ws, uint64_t *out, pi_status *status, hipStream_t st) {
-  const int grid_max = resident_grid();
   size_t table_bytes = 0;
   for (ClassPlan &c : bp.cls) {
     for (FinQuery &f : c.fins) f.want_status = status != nullptr ? 1u : 0u;
@@ -433,7 +474,7 @@ int run_batch(BatchPlan &bp, char *ws, uint64_t *out, pi_status *status, hipStre
   }
   if (hipEventRecord(sg->done, st) != hipSuccess) return PI_EDEVICE;
   sg->pending = true;
-  return launch_planned(bp, ws, out, status, grid_max, st);
+  return launch_planned(bp, ws, out, status, st);
 }
 
 }  // namespace host
@@ -501,15 +542,15 @@ struct pi_batch {
   char *ws = nullptr;
   uint64_t *out = nullptr;
   pi_status *status = nullptr;
-  int grid_max = 2048;
 };
 
 namespace pibbp {
 namespace host {
 // Kernel launches of a planned batch whose tables are already on the device.
-int launch_planned(const BatchPlan &bp, char *ws, uint64_t *out, pi_status *status, int grid_max,
+int launch_planned(const BatchPlan &bp, char *ws, uint64_t *out, pi_status *status,
                    hipStream_t st) {
   for (const ClassPlan &c : bp.cls) {
+    const int grid_max = c.grid;
     auto *acc = (unsigned long long *)(ws + c.acc_off);
     auto *segs = (HeadSeg *)(ws + c.seg_off);
     auto *fins = (FinQuery *)(ws + c.fin_off);
@@ -559,14 +600,13 @@ int pi_batch_create(const pi_query *q, int count, uint64_t *out, pi_status *stat
   }
   b->out = out;
   b->status = status;
-  b->grid_max = resident_grid();
   *plan = b;
   return PI_OK;
 }
 
 int pi_batch_launch(pi_batch *plan, hipStream_t stream) {
   if (!plan) return PI_EINVAL;
-  return launch_planned(plan->bp, plan->ws, plan->out, plan->status, plan->grid_max, stream);
+  return launch_planned(plan->bp, plan->ws, plan->out, plan->status, stream);
 }
 
 void pi_batch_destroy(pi_batch *plan) {
@@ -597,6 +637,26 @@ int pi_extract_batch(const pi_query *q, int count, uint64_t *out, pi_status *sta
     if (!ws) return err;
   }
   return run_batch(bp, ws, out, status, stream);
+}
+
+int pi_set_tuning(int limbs, uint32_t wg_per_cu, uint32_t run_cap) {
+  if (limbs < 0 || limbs > PI_MAX_L || run_cap == 0 || run_cap > 4096 || wg_per_cu > 64)
+    return PI_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (int L = 1; L <= PI_MAX_L; ++L)
+    if (limbs == 0 || L == limbs) {
+      g_tune[L].wg_per_cu = wg_per_cu;
+      g_tune[L].run_cap = run_cap;
+    }
+  return PI_OK;
+}
+
+int pi_get_tuning(int limbs, uint32_t *wg_per_cu, uint32_t *run_cap) {
+  if (limbs < 1 || limbs > PI_MAX_L || !wg_per_cu || !run_cap) return PI_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  *wg_per_cu = g_tune[limbs].wg_per_cu;
+  *run_cap = g_tune[limbs].run_cap;
+  return PI_OK;
 }
 
 const char *pi_strerror(int code) {

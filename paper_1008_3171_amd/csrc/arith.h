@@ -15,18 +15,82 @@
 //  * truncation to P bits: floor(t / 2^(64L-P)) = floor(r*2^P/M), so the P-bit
 //    term, left-aligned in L limbs, is t with its low 64L-P bits cleared.
 //
-// Two modulus classes keep the multiply count down:
+// Modulus classes keep the instruction count down:
 //  * class 32 (M < 2^31): R = 2^32, residues kept below M;
-//  * class 62 (2^31 <= M < 2^54): R = 2^62, residues in two 31-bit digits,
-//    kept below 8M (the head kernel);
+//  * binary64 (2^31 <= M < 2^48): plain (not Montgomery) residues held
+//    exactly in doubles; a squaring is six full-rate fp64 instructions
+//    against sixteen integer ones for the same modulus in class 62;
+//  * class 62 (2^48 <= M < 2^54): R = 2^62, residues in two 31-bit digits,
+//    kept below 8M;
 //  * R = 2^64 with residues below 2M (M < 2^60): the few tail terms.
-// v_mad_u64_u32 issues at full rate on gfx950, so these are written in plain
-// 64-bit C and the compiler emits mad chains.
+// v_mad_u64_u32 issues at full rate on gfx950, so the integer classes are
+// written in plain 64-bit C and the compiler emits mad chains.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace pibbp {
+
+// ---- binary64 residues, 2^31 <= M < 2^48 -----------------------------------
+//
+// A residue is an integer-valued double x with |x| < M (signed, not reduced).
+// One step computes y = 2^d x^2 - qM:
+//   H + Lo = x (2^d x) exactly (H the rounded product, Lo its error, from an
+//   FMA), q = rint(H * inv) with inv within 2^-51 of 1/M relatively, and
+//   y = (H - qM) + Lo, where the FMA gives H - qM exactly (an integer below
+//   2^53 in magnitude) and the last sum is exact for the same reason.
+// Bound: |H/M - q| <= 1/2 + (H/M)(2^-51 + 2^-53) and |Lo| <= 2^-53 H, so
+// |y| <= M/2 + 3 * 2^-52 * 2^d * M^2, which is below M while
+// 2^d M <= 2^52 / 6 (about 2^49.4). Two-bit windows (d <= 3) are therefore
+// exact for M < 2^46 and one-bit windows (d <= 1) for M < 2^48.
+
+// One Newton step toward 1/m from r: relative error e becomes e^2 + 2^-53.
+// From 1/(M - 2a), at most 2^-26.6 away for M >= 2^31 and a <= 10, one step
+// lands within 2^-52.2.
+__device__ __forceinline__ double recip_step(double m, double r) {
+#pragma clang fp contract(off)
+  const double e = __builtin_fma(-m, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
+__device__ __forceinline__ double recip_f64(double m) {
+  return recip_step(m, recip_step(m, __builtin_amdgcn_rcp(m)));
+}
+
+// y = 2^d x^2 mod M, |y| < M (bounds above).
+__device__ __forceinline__ double sqr_f64(double x, int d, double M, double inv) {
+#pragma clang fp contract(off)
+  const double xs = __builtin_amdgcn_ldexp(x, d);
+  const double h = x * xs;
+  const double lo = __builtin_fma(x, xs, -h);
+  const double q = __builtin_rint(h * inv);
+  return __builtin_fma(-q, M, h) + lo;
+}
+
+__device__ __forceinline__ double sqr_f64(double x, double M, double inv) {
+#pragma clang fp contract(off)
+  const double h = x * x;
+  const double lo = __builtin_fma(x, x, -h);
+  const double q = __builtin_rint(h * inv);
+  return __builtin_fma(-q, M, h) + lo;
+}
+
+// 2^v mod M, |result| < M, for v < 64 and M >= 2^31: the error term
+// 2^v (2^-51 + 2^-53) is below 2^13, far under M/2.
+__device__ __forceinline__ double pow2_f64(uint32_t v, double M, double inv) {
+#pragma clang fp contract(off)
+  const double p = __builtin_amdgcn_ldexp(1.0, (int)v);
+  const double q = __builtin_rint(p * inv);
+  return __builtin_fma(-q, M, p);
+}
+
+// The residue in [0, M) as an integer: adding 2^52 to an integer-valued
+// double in [0, 2^52) puts the integer in the significand field.
+__device__ __forceinline__ uint64_t residue_u64(double x, double M) {
+#pragma clang fp contract(off)
+  const double y = (x < 0.0 ? x + M : x) + 0x1p52;
+  return (uint64_t)__double_as_longlong(y) & ((1ull << 52) - 1u);
+}
 
 // -M^-1 mod 2^32, M odd. (3M) xor 2 is an inverse to 5 bits; each Newton step
 // x <- x(2 - Mx) doubles the number of correct low bits (5, 10, 20, 40).
@@ -195,18 +259,30 @@ __device__ __forceinline__ uint32_t mont_one32(uint32_t M) {
 
 // ---- limb vectors ---------------------------------------------------------
 
+// L-limb add and negate mod 2^(64L), written on 32-bit halves so that the
+// compiler emits one v_add_co / v_addc_co (v_sub_co / v_subb_co) carry chain,
+// two instructions per limb.
 template <int L>
 __device__ __forceinline__ void add_limbs(uint64_t (&acc)[L], const uint64_t (&t)[L]) {
-  uint64_t c = 0;
+  unsigned int c = 0;
 #pragma unroll
-  for (int i = 0; i < L; ++i) acc[i] = __builtin_addcll(acc[i], t[i], c, (unsigned long long *)&c);
+  for (int i = 0; i < L; ++i) {
+    const unsigned int lo = __builtin_addc((unsigned int)acc[i], (unsigned int)t[i], c, &c);
+    const unsigned int hi =
+        __builtin_addc((unsigned int)(acc[i] >> 32), (unsigned int)(t[i] >> 32), c, &c);
+    acc[i] = ((uint64_t)hi << 32) | lo;
+  }
 }
 
 template <int L>
 __device__ __forceinline__ void neg_limbs(uint64_t (&x)[L]) {
-  uint64_t c = 0;
+  unsigned int c = 0;
 #pragma unroll
-  for (int i = 0; i < L; ++i) x[i] = __builtin_subcll(0ull, x[i], c, (unsigned long long *)&c);
+  for (int i = 0; i < L; ++i) {
+    const unsigned int lo = __builtin_subc(0u, (unsigned int)x[i], c, &c);
+    const unsigned int hi = __builtin_subc(0u, (unsigned int)(x[i] >> 32), c, &c);
+    x[i] = ((uint64_t)hi << 32) | lo;
+  }
 }
 
 // t = -s * M^-1 mod 2^(64L): the L-limb quotient floor(r 2^(64L) / M) when
@@ -220,6 +296,31 @@ __device__ __forceinline__ void hensel64(uint64_t s, uint64_t M, uint64_t mp, ui
     uint64_t ti = h * mp;
     h = __umul64hi(ti, M) + (h != 0u ? 1u : 0u);
     t[i] = ti;
+  }
+}
+
+// The same quotient from 32-bit digits for any odd M < 2^62, with only
+// mp32 = -M^-1 mod 2^32. Digit u = lo32(h) * mp32 makes h + uM divisible by
+// 2^32. With M = m1 2^31 + m0 (m0 < 2^31): A = u m0 + h stays below 2^64 and
+// is divisible by 2^31, and h' = (h + uM) / 2^32 = (u m1 + A / 2^31) / 2.
+// h stays below M. Each digit is a multiply, two full-rate multiply-adds and
+// two 64-bit shifts, all on aligned register pairs.
+template <int L>
+__device__ __forceinline__ void hensel_d32(uint64_t s, uint64_t M, uint32_t mp32,
+                                           uint64_t (&t)[L]) {
+  const uint32_t m0 = (uint32_t)M & 0x7fffffffu, m1 = (uint32_t)(M >> 31);
+  uint64_t h = s;
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    uint32_t dg[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const uint32_t u = (uint32_t)h * mp32;
+      const uint64_t A = mad64(u, m0, h);
+      h = mad64(u, m1, A >> 31) >> 1;
+      dg[j] = u;
+    }
+    t[i] = ((uint64_t)dg[1] << 32) | dg[0];
   }
 }
 
@@ -239,6 +340,11 @@ __device__ __forceinline__ void hensel32(uint32_t s, uint32_t M, uint32_t mp32, 
 
 // Masks that clear the low 64L-P bits of an L-limb value (P <= 64L); built
 // once per chunk, applied to every term with one AND per 32-bit word.
+// Limbs of a kernel limb class L that can hold cleared bits: a query uses the
+// smallest class with 64L >= P, so 64L - P < 64 (L - previous class), and only
+// that many low limbs need a mask (classes 1..6, 8, 12, 17).
+constexpr int masked_limbs(int L) { return L == 8 ? 2 : L == 12 ? 4 : L == 17 ? 5 : 1; }
+
 template <int L>
 __device__ __forceinline__ void low_masks(uint32_t P, uint64_t (&m)[L]) {
   const uint32_t z = 64u * L - P;
@@ -249,18 +355,21 @@ __device__ __forceinline__ void low_masks(uint32_t P, uint64_t (&m)[L]) {
   }
 }
 
+// Apply the masks of the low limbs that can need one (see masked_limbs).
 template <int L>
 __device__ __forceinline__ void apply_masks(uint64_t (&t)[L], const uint64_t (&m)[L]) {
 #pragma unroll
-  for (int i = 0; i < L; ++i) t[i] &= m[i];
+  for (int i = 0; i < masked_limbs(L); ++i) t[i] &= m[i];
 }
 
-// Clear the low 64L-P bits (P <= 64L), for the few terms outside the hot loop.
+// Clear the low 64L-P bits (any P <= 64L), for the few terms outside the hot
+// loop.
 template <int L>
 __device__ __forceinline__ void clip_low(uint64_t (&t)[L], uint32_t P) {
   uint64_t m[L];
   low_masks<L>(P, m);
-  apply_masks<L>(t, m);
+#pragma unroll
+  for (int i = 0; i < L; ++i) t[i] &= m[i];
 }
 
 }  // namespace pibbp

@@ -27,11 +27,12 @@ int make_plan(int formula, uint64_t n, uint32_t w, uint32_t P, uint32_t jmask, u
               uint64_t k1, QueryPlan *qp);
 void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &out);
 uint64_t number_chunks(std::vector<HeadSeg> &segs, uint32_t run_cap, uint64_t chunk_base);
-uint32_t pick_run(uint64_t head_terms, int grid);
+uint32_t pick_run(uint64_t head_terms, int grid, uint32_t cap);
+uint32_t run_cap_for(int Lk);
 uint32_t min_run_cap(uint64_t head_terms);
 FinQuery fin_query(const QueryPlan &qp, uint64_t out_off, uint32_t status_mode, uint32_t sidx,
                    uint32_t acc_off);
-int resident_grid();
+int resident_grid(int Lk);
 int hip_err(hipError_t e);
 
 }  // namespace host

@@ -179,9 +179,9 @@ __device__ __forceinline__ void lane_run62(uint64_t k0, uint32_t run, uint32_t p
     // past the chunk, so is every lane, and its X bounds the ladder length.
     if (uniform64(k) >= kend) break;
     const int nb0 = bitlen64(uniform64(X));
-    const uint64_t mp = neg_inv64(M);
+    const uint32_t mp32 = neg_inv32((uint32_t)M);
     const uint32_t m0 = (uint32_t)M & kMask31, m1 = (uint32_t)(M >> 31);
-    const uint32_t p = (uint32_t)mp & kMask31;
+    const uint32_t p = mp32 & kMask31;
     // the top t exponent bits v go into the start value: g 2^v == 2^(62+v)
     // is the Montgomery form of 2^v, so t squarings are skipped
     const int tb = pre < (uint32_t)nb0 ? (int)pre : nb0;
@@ -197,9 +197,64 @@ __device__ __forceinline__ void lane_run62(uint64_t k0, uint32_t run, uint32_t p
     x = x >= 2u * M ? x - 2u * M : x;
     x = x >= M ? x - M : x;
     uint64_t t[L];
-    hensel64<L>(x, M, mp, t);
+    hensel_d32<L>(x, M, mp32, t);
     apply_masks<L>(t, msk);
     if (k < kend) add_limbs<L>(sum, t);
+  }
+}
+
+// Binary64 terms of one lane, 2^31 <= M < 2^48 (W = 2 for M < 2^46, else
+// W = 1): s = 2^X mod M with X = E + 64L by a left-to-right ladder over
+// W-bit windows (W squarings, the window's value folded into the last one as
+// a power of two). The top t <= 6 bits v of X give the start 2^v mod M
+// directly; t is chosen so that the remaining bit count is a multiple of W,
+// which also keeps every two-bit window inside one 32-bit half of X. The
+// reciprocal of each modulus comes from the previous one by a Newton step.
+template <int L, int W>
+__device__ __forceinline__ void lane_runf(uint64_t k0, uint32_t run, uint64_t kend, uint64_t a,
+                                          uint64_t b, uint64_t dc, uint64_t step, uint32_t P,
+                                          uint64_t (&sum)[L]) {
+  const uint64_t dM = 2u * a, dX = 2u * step;
+  uint64_t M = a * k0 + b;
+  uint64_t X = dc + 64ull * L - step * k0;
+  double Md = (double)M;
+  const double dMd = (double)dM;
+  double inv = recip_f64(Md);
+  uint64_t msk[L];
+  low_masks<L>(P, msk);
+  for (uint32_t i = 0; i < run; ++i, M += dM, X -= dX) {
+    const uint64_t k = k0 + 2ull * i;
+    if (uniform64(k) >= kend) break;
+    const int nb = bitlen64(uniform64(X));
+    int tb;
+    if (W == 2)
+      tb = nb <= 6 ? nb : 6 - ((nb - 6) & 1);
+    else
+      tb = nb < 6 ? nb : 6;
+    const int rest = nb - tb;
+    double x = pow2_f64((uint32_t)(X >> rest), Md, inv);
+    const uint32_t xl = (uint32_t)X, xh = (uint32_t)(X >> 32);
+    if (W == 2) {
+      for (int p = rest - 2; p >= 32; p -= 2) {
+        x = sqr_f64(x, Md, inv);
+        x = sqr_f64(x, (int)((xh >> (p - 32)) & 3u), Md, inv);
+      }
+      for (int p = (rest < 32 ? rest : 32) - 2; p >= 0; p -= 2) {
+        x = sqr_f64(x, Md, inv);
+        x = sqr_f64(x, (int)((xl >> p) & 3u), Md, inv);
+      }
+    } else {
+      for (int p = rest - 1; p >= 32; --p) x = sqr_f64(x, (int)((xh >> (p - 32)) & 1u), Md, inv);
+      for (int p = (rest < 32 ? rest : 32) - 1; p >= 0; --p)
+        x = sqr_f64(x, (int)((xl >> p) & 1u), Md, inv);
+    }
+    const uint64_t sres = residue_u64(x, Md);  // == 2^(E + 64L) (mod M), in [0, M)
+    uint64_t t[L];
+    hensel_d32<L>(sres, M, neg_inv32((uint32_t)M), t);
+    apply_masks<L>(t, msk);
+    if (k < kend) add_limbs<L>(sum, t);
+    Md += dMd;
+    inv = recip_step(Md, inv);
   }
 }
 
@@ -281,6 +336,8 @@ __device__ void head_chunks(const HeadSeg *segs, int nseg, uint64_t nchunks,
     for (int i = 0; i < L; ++i) sum[i] = 0;
     switch (sg.cls) {
       case 64: lane_run62<L>(k0, run, sg.pre, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+      case 48: lane_runf<L, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+      case 46: lane_runf<L, 2>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
       case 31: lane_run32<L, false, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
       case 29: lane_run32<L, true, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
       default: lane_run32<L, true, false>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
@@ -551,6 +608,31 @@ hipError_t launch_combine(const uint64_t *parts, int count, int Lq, uint32_t P, 
   hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(256), 0, st, parts, count, Lq, P, w, nterms, J,
                      out, status);
   return hipGetLastError();
+}
+
+template <int L>
+static int occupancy_L() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, head_kernel_ptr<L>, 256, 0) != hipSuccess)
+    return 0;
+  return n;
+}
+
+int head_occupancy(int Lk) {
+#define C(L) occupancy_L<L>()
+  switch (Lk) {
+    case 1: return C(1);
+    case 2: return C(2);
+    case 3: return C(3);
+    case 4: return C(4);
+    case 5: return C(5);
+    case 6: return C(6);
+    case 8: return C(8);
+    case 12: return C(12);
+    case 17: return C(17);
+    default: return 0;
+  }
+#undef C
 }
 
 hipError_t launch_zero(unsigned long long *p, uint64_t n, hipStream_t st) {

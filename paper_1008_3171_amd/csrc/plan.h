@@ -8,7 +8,7 @@
 namespace pibbp {
 
 constexpr int PI_MAX_L = 17;          // ceil(PI_MAX_P / 64)
-constexpr int kMaxArgSegs = 35;       // 7 series x 5 modulus ranges
+constexpr int kMaxArgSegs = 42;       // 7 series x 6 modulus ranges
 
 // A range [kb, ke) of head indices (E >= 0) of series j of one query, all of
 // one modulus class; its chunks are numbered chunk0, chunk0 + 1, ...
@@ -53,6 +53,8 @@ hipError_t launch_finalize(int Lk, const FinQuery &single, const FinQuery *qs, i
                            const unsigned long long *acc, uint64_t *out, pi_status *status,
                            hipStream_t st);
 hipError_t launch_zero(unsigned long long *p, uint64_t n, hipStream_t st);
+// Workgroups of the head kernel instance for Lk limbs that fit on one CU.
+int head_occupancy(int Lk);
 hipError_t launch_combine(const uint64_t *parts, int count, int Lq, uint32_t P, uint32_t w,
                           uint64_t nterms, uint32_t J, uint64_t *out, pi_status *status,
                           hipStream_t st);

@@ -49,7 +49,6 @@ struct pi_server {
   hipStream_t st = nullptr;
   uint32_t cap = 0;
   uint64_t step_terms = 0;
-  int grid_max = 2048;
   unsigned long long *acc = nullptr;  // cap x kSlotCounters
   uint64_t *res = nullptr;            // cap x PI_MAX_L limbs, rows in finish order
   pi_status *res_st = nullptr;        // cap
@@ -120,7 +119,6 @@ int pi_server_create(uint32_t max_active, uint64_t step_terms, hipStream_t strea
   s->st = stream;
   s->cap = cap;
   s->step_terms = step_terms;
-  s->grid_max = resident_grid();
   if (hipMalloc((void **)&s->acc, (size_t)cap * kSlotCounters * 8u) != hipSuccess ||
       hipMalloc((void **)&s->res, (size_t)cap * PI_MAX_L * 8u) != hipSuccess ||
       hipMalloc((void **)&s->res_st, (size_t)cap * sizeof(pi_status)) != hipSuccess) {
@@ -145,7 +143,8 @@ int pi_server_submit(pi_server *s, const pi_query *q, uint64_t tag) {
   s->free_slots.pop_back();
   a.tag = tag;
   head_segments(a.qp, a.slot * kSlotCounters, a.segs);
-  const uint32_t cap = std::max(pick_run(a.qp.nhead, s->grid_max), min_run_cap(a.qp.nhead));
+  const uint32_t cap = std::max(pick_run(a.qp.nhead, resident_grid(a.qp.Lk), run_cap_for(a.qp.Lk)),
+                                min_run_cap(a.qp.nhead));
   a.nchunks = number_chunks(a.segs, cap, 0);
   s->active.push_back(std::move(a));
   return PI_OK;
@@ -223,7 +222,7 @@ int pi_server_step(pi_server *s, uint32_t *finished) {
     const int Lk = kv.first;
     const uint64_t nch = chunks_by_class[Lk];
     if (!nch) continue;
-    const int grid = (int)std::min<uint64_t>(nch, (uint64_t)s->grid_max);
+    const int grid = (int)std::min<uint64_t>(nch, (uint64_t)resident_grid(Lk));
     if (int e = hip_err(launch_head_ptr(Lk, s->dsegs + kv.second.first, (int)kv.second.second, nch,
                                         grid, s->acc, s->st)))
       return e;

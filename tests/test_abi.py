@@ -63,3 +63,15 @@ def test_invalid_arguments_are_rejected_synchronously():
     # moduli from 2^54 up are outside the supported range
     assert lib.pi_extract_ex(1, 2 ** 61, 8, 72, dummy, null, null) == -4
     assert lib.pi_extract_ex(1, 2 ** 55, 8, 72, dummy, null, null) == -4
+
+
+def test_tuning_roundtrip_and_limits():
+    lib = pb.load()
+    before = pb.get_tuning(5)
+    pb.set_tuning(5, 6, 32)
+    assert pb.get_tuning(5) == (6, 32)
+    pb.set_tuning(5, *before)
+    assert pb.get_tuning(5) == before
+    assert lib.pi_set_tuning(5, 0, 0) == -1          # run cap 0
+    assert lib.pi_set_tuning(18, 0, 64) == -1        # no such limb count
+    assert lib.pi_set_tuning(5, 65, 64) == -1

@@ -64,20 +64,23 @@ def test_config1_bellard_1e6():
     assert want[2]
 
 
-def test_slices_across_the_modulus_class_boundary():
-    # class 32 ends at M = 2^31; check ranges straddling it, for every series
-    rng = random.Random(5)
+@pytest.mark.parametrize("cut", [22, 29, 31, 46, 48])
+def test_slices_across_every_modulus_class_boundary(cut):
+    # the head kernel switches arithmetic where the modulus reaches 2^22, 2^29,
+    # 2^31 (integer classes), 2^46 and 2^48 (binary64 windows, then R = 2^62):
+    # ranges straddling each cut for every series, with exponents just past
+    # the cut and near 2^61 (both halves of a 64-bit exponent)
+    rng = random.Random(5 + cut)
     for f in FORMULAS:
         rows, step, _ = oracle.series_table(f)
         for j, (s, c, a, b) in enumerate(rows):
-            ks = (2 ** 31 - b + a - 1) // a
-            n = step * ks + 10 ** 6
-            for _ in range(3):
+            ks = (2 ** cut - b + a - 1) // a
+            for n in (step * ks + 10 ** 6, 2 ** 61 + rng.randrange(10 ** 6)):
                 k0 = ks - rng.randrange(0, 3000)
                 k1 = ks + rng.randrange(1, 3000)
                 P = rng.choice([96, 320, 1088])
                 assert gpu_slice(f, j, n, k0, k1, P) == \
-                    oracle.sum_slice(f, j, n - 1, k0, k1, P, 8)[0], (f, j, k0, k1, P)
+                    oracle.sum_slice(f, j, n - 1, k0, k1, P, 8)[0], (f, j, n, k0, k1, P)
 
 
 def test_slices_large_moduli():
@@ -168,3 +171,19 @@ def test_table_2_2_rows_all_printed_bits(m):
     S, N, cert = gpu_extract(pb.BELLARD, n, nbits, 1088)
     assert cert
     assert S >> (1088 - nbits) == hex_bits(row[3], nbits)
+
+
+def test_results_do_not_depend_on_launch_shape():
+    # the chunk partition changes with the launch shape; the sums must not
+    saved = {L: pb.get_tuning(L) for L in (2, 5)}
+    try:
+        ref = {q: gpu_extract(*q) for q in ((pb.BELLARD, 3 * 10 ** 8 + 7, 256, 320),
+                                            (pb.BBP, 2 * 10 ** 8 + 1, 64, 128))}
+        for wg, cap in ((1, 1), (3, 7), (16, 128), (0, 64)):
+            for L in (2, 5):
+                pb.set_tuning(L, wg, cap)
+            for q, want in ref.items():
+                assert gpu_extract(*q) == want, (wg, cap, q)
+    finally:
+        for L, (wg, cap) in saved.items():
+            pb.set_tuning(L, wg, cap)
