@@ -82,36 +82,40 @@ def _pre_bits(run, Mmin, Mmax, a):
     return 0
 
 
-# VALU instructions of the head kernel's data path, from the compiled gfx950
-# code (loop control and scheduling excluded): per exponent bit of the ladder,
-# and per term for everything else (start value, reciprocal or -M^-1, the
-# residue, the L-limb Hensel division at L = 5, masks and the accumulation).
-#   class: (first modulus, per bit, per term, X offset - 64L)
+# VALU instructions of the head kernel's data path per head term, from the
+# compiled gfx950 code (loop control and scheduling excluded):
+#  * binary64 classes (2^31 <= M < 2^48, windows of W = 3, 2, 1 bits): the
+#    top 6 bits of X = E + 64L are the start value; each remaining bit costs
+#    a squaring (6 instructions), each whole window 2 more (exponent digit,
+#    scale) and a short leading window 3 more; 100 per term for the start,
+#    reciprocal, residue, 32-bit inverse, the ten-digit Hensel division at
+#    L = 5, the mask and the accumulation;
+#  * integer classes (Montgomery): a fixed cost per ladder bit of
+#    X = E + 64L + offset (class 62 folds `pre` top bits into its start).
+#   (name, first modulus, W, per bit, per term, X offset - 64L)
 KERNEL_CLASSES = [
-    ("22", 0, 5, 77, -32),         # R = 2^32, lazy, start by doublings
-    ("29", 2 ** 22, 5, 71, -32),   # R = 2^32, lazy, run-quotient start
-    ("31", 2 ** 29, 7, 71, -32),   # R = 2^32, reduced residues
-    ("f2", 2 ** 31, 7, 99, 0),    # binary64, two-bit windows
-    ("f1", 2 ** 46, 8, 101, 0),    # binary64, one-bit windows
-    ("62", 2 ** 48, 16, 116, -62), # R = 2^62, two 31-bit digits
+    ("22", 0, 1, 5, 77, -32),         # R = 2^32, lazy, start by doublings
+    ("29", 2 ** 22, 1, 5, 71, -32),   # R = 2^32, lazy, run-quotient start
+    ("31", 2 ** 29, 1, 7, 71, -32),   # R = 2^32, reduced residues
+    ("f3", 2 ** 31, 3, 6, 100, 0),    # binary64, three-bit windows
+    ("f2", 2 ** 42, 2, 6, 100, 0),    # binary64, two-bit windows
+    ("f1", 2 ** 46, 1, 6, 101, 0),    # binary64, one-bit windows
+    ("62", 2 ** 48, 1, 16, 116, -62), # R = 2^62, two 31-bit digits
 ]
 
 
-def _start_bits(cls, nb, pre):
-    if cls == "f2":
-        return nb if nb <= 6 else 6 - ((nb - 6) & 1)
-    if cls == "f1":
-        return min(nb, 6)
-    if cls == "62":
-        return min(pre, nb)
-    return 0
+def _term_ops(cls, W, per_bit, fixed, nb, pre):
+    if cls[0] == "f":
+        rest = max(0, nb - 6)
+        return fixed + per_bit * rest + 2 * (rest // W) + (3 if rest % W else 0)
+    start = min(pre, nb) if cls == "62" else 0
+    return fixed + per_bit * (nb - start)
 
 
 def valu_ops_per_launch(formula, n, P, run=64):
-    """Data-path VALU instructions of every head term of one extraction:
-    per term, (ladder bits) x (per bit) + (per term) for the term's modulus
-    class, with the ladder running over X = E + 64L + offset minus the start
-    bits. Returns (ops, head terms)."""
+    """Data-path VALU instructions of every head term of one extraction (the
+    per-term model above, summed over the bands of equal bitlen(X) of each
+    series and modulus class). Returns (ops, head terms)."""
     rows, step = series(formula)
     L = (P + 63) // 64
     d = n - 1
@@ -125,8 +129,8 @@ def valu_ops_per_launch(formula, n, P, run=64):
         def first_k(mlim):
             return min(K, max(0, -(-(mlim - b) // a)))
 
-        bounds = [first_k(m) for _, m, _, _, _ in KERNEL_CLASSES] + [K]
-        for i, (cls, _, per_bit, fixed, off) in enumerate(KERNEL_CLASSES):
+        bounds = [first_k(m) for _, m, _, _, _, _ in KERNEL_CLASSES] + [K]
+        for i, (cls, _, W, per_bit, fixed, off) in enumerate(KERNEL_CLASSES):
             lo, hi = bounds[i], bounds[i + 1]
             if lo >= hi:
                 continue
@@ -142,7 +146,7 @@ def valu_ops_per_launch(formula, n, P, run=64):
                 lowX = 1 << (bl - 1) if bl > 0 else 0
                 kmax = min(hi - 1, (base - lowX) // step) if bl > 0 else hi - 1
                 cnt = kmax - k + 1
-                total += cnt * ((bl - _start_bits(cls, bl, pre)) * per_bit + fixed)
+                total += cnt * _term_ops(cls, W, per_bit, fixed, bl, pre)
                 terms += cnt
                 k = kmax + 1
     return total, terms

@@ -22,8 +22,8 @@ WORKLOADS = {
     3: (1, 10 ** 10, 128, 192),
     5: (1, 10 ** 11, 256, 320),
 }
-WG_PER_CU = (0, 2, 3, 4, 5, 6, 8, 12, 16)
-RUN_CAPS = (32, 64, 128)
+WG_PER_CU = (0, 4, 8, 12, 16, 24)
+RUN_CAPS = (64, 128, 256, 512)
 
 
 def time_one(pb, torch, spec, reps=2):

@@ -94,11 +94,12 @@ int make_plan(int formula, uint64_t n, uint32_t w, uint32_t P, uint32_t jmask, u
 
 // Head segments of a plan, split by modulus range: below 2^22 (R = 2^32,
 // Montgomery one by doublings), [2^22, 2^29) (R = 2^32, lazy residues),
-// [2^29, 2^31) (R = 2^32), [2^31, 2^46) (binary64, two-bit windows),
-// [2^46, 2^48) (binary64, one-bit windows) and from 2^48 (R = 2^62).
+// [2^29, 2^31) (R = 2^32), [2^31, 2^42), [2^42, 2^46) and [2^46, 2^48)
+// (binary64 with three-, two- and one-bit windows) and from 2^48 (R = 2^62).
 void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &out) {
-  static const uint64_t kLim[5] = {1ull << 22, 1ull << 29, kClass32Limit, 1ull << 46, 1ull << 48};
-  static const uint32_t kCls[6] = {22, 29, 31, 46, 48, 64};
+  static const uint64_t kLim[6] = {1ull << 22, 1ull << 29, kClass32Limit,
+                                   1ull << 42, 1ull << 46,  1ull << 48};
+  static const uint32_t kCls[7] = {22, 29, 31, 42, 46, 48, 64};
   for (int j = 0; j < kHJ[qp.formula]; ++j) {
     const HostSeries &s = kHSeries[qp.formula][j];
     const uint64_t kb = qp.hk0[j], ke = qp.hk1[j];
@@ -107,8 +108,14 @@ void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &
       const uint64_t k = Mlim > s.b ? (Mlim - s.b + s.a - 1) / s.a : 0;
       return std::min(std::max(k, kb), ke);
     };
-    const uint64_t cuts[7] = {kb,           first_k(kLim[0]), first_k(kLim[1]), first_k(kLim[2]),
-                              first_k(kLim[3]), first_k(kLim[4]), ke};
+    const uint64_t cuts[8] = {kb,
+                              first_k(kLim[0]),
+                              first_k(kLim[1]),
+                              first_k(kLim[2]),
+                              first_k(kLim[3]),
+                              first_k(kLim[4]),
+                              first_k(kLim[5]),
+                              ke};
     HeadSeg g;
     memset(&g, 0, sizeof g);
     g.d = qp.d;
@@ -116,7 +123,7 @@ void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &
     g.j = (uint32_t)j;
     g.P = qp.P;
     g.acc_off = acc_off;
-    for (int c = 0; c < 6; ++c) {
+    for (int c = 0; c < 7; ++c) {
       if (cuts[c] >= cuts[c + 1]) continue;
       g.kb = cuts[c];
       g.ke = cuts[c + 1];
@@ -376,12 +383,15 @@ int run_single(const QueryPlan &qp, uint64_t *out, pi_status *status, uint32_t m
   tab.n = (int)segs.size();
   const int Lk = qp.Lk;
   int err = PI_OK;
-  auto *acc = (unsigned long long *)arena(st, 2u * PI_MAX_L * sizeof(unsigned long long), &err);
+  // 2Lk carry-save counters, then the head launch's chunk counter
+  auto *acc =
+      (unsigned long long *)arena(st, (2u * PI_MAX_L + 1u) * sizeof(unsigned long long), &err);
   if (!acc) return err;
-  if (int e = hip_err(launch_zero(acc, 2u * (uint64_t)Lk, st))) return e;
+  if (int e = hip_err(launch_zero(acc, 2u * (uint64_t)Lk + 1u, st))) return e;
   if (nchunks) {
     const int grid = (int)std::min<uint64_t>(nchunks, (uint64_t)grid_max);
-    if (int e = hip_err(launch_head_args(Lk, tab, nchunks, grid, acc, st))) return e;
+    if (int e = hip_err(launch_head_args(Lk, tab, nchunks, grid, acc, acc + 2u * Lk, st)))
+      return e;
   }
   FinQuery fq = fin_query(qp, 0, status != nullptr ? mode : 0u, 0, 0);
   return hip_err(launch_finalize(Lk, fq, nullptr, 1, acc, out, status, st));
@@ -433,8 +443,8 @@ int plan_batch(const pi_query *q, int count, BatchPlan *bp) {
   }
   size_t off = 0;
   for (ClassPlan &c : bp->cls) {
-    c.acc_off = off;
-    off = align256(off + c.fins.size() * 2u * (size_t)c.Lk * sizeof(unsigned long long));
+    c.acc_off = off;  // carry-save counters of each query, then the chunk counter
+    off = align256(off + (c.fins.size() * 2u * (size_t)c.Lk + 1u) * sizeof(unsigned long long));
     c.seg_off = off;
     off = align256(off + c.segs.size() * sizeof(HeadSeg));
     c.fin_off = off;
@@ -554,10 +564,12 @@ int launch_planned(const BatchPlan &bp, char *ws, uint64_t *out, pi_status *stat
     auto *acc = (unsigned long long *)(ws + c.acc_off);
     auto *segs = (HeadSeg *)(ws + c.seg_off);
     auto *fins = (FinQuery *)(ws + c.fin_off);
-    if (int e = hip_err(launch_zero(acc, c.fins.size() * 2u * (uint64_t)c.Lk, st))) return e;
+    const uint64_t ncount = c.fins.size() * 2u * (uint64_t)c.Lk;
+    if (int e = hip_err(launch_zero(acc, ncount + 1u, st))) return e;
     if (c.nchunks) {
       const int grid = (int)std::min<uint64_t>(c.nchunks, (uint64_t)grid_max);
-      if (int e = hip_err(launch_head_ptr(c.Lk, segs, (int)c.segs.size(), c.nchunks, grid, acc, st)))
+      if (int e = hip_err(launch_head_ptr(c.Lk, segs, (int)c.segs.size(), c.nchunks, grid, acc,
+                                          acc + ncount, st)))
         return e;
     }
     FinQuery none;

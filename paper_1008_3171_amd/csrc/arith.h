@@ -19,7 +19,8 @@
 //  * class 32 (M < 2^31): R = 2^32, residues kept below M;
 //  * binary64 (2^31 <= M < 2^48): plain (not Montgomery) residues held
 //    exactly in doubles; a squaring is six full-rate fp64 instructions
-//    against sixteen integer ones for the same modulus in class 62;
+//    against sixteen integer ones for the same modulus in class 62, and
+//    exponent windows of up to three bits cost one more per window;
 //  * class 62 (2^48 <= M < 2^54): R = 2^62, residues in two 31-bit digits,
 //    kept below 8M;
 //  * R = 2^64 with residues below 2M (M < 2^60): the few tail terms.
@@ -41,8 +42,9 @@ namespace pibbp {
 //   2^53 in magnitude) and the last sum is exact for the same reason.
 // Bound: |H/M - q| <= 1/2 + (H/M)(2^-51 + 2^-53) and |Lo| <= 2^-53 H, so
 // |y| <= M/2 + 3 * 2^-52 * 2^d * M^2, which is below M while
-// 2^d M <= 2^52 / 6 (about 2^49.4). Two-bit windows (d <= 3) are therefore
-// exact for M < 2^46 and one-bit windows (d <= 1) for M < 2^48.
+// 2^d M <= 2^52 / 6 (about 2^49.4). Three-bit windows (d <= 7) are therefore
+// exact for M < 2^42, two-bit windows (d <= 3) for M < 2^46 and one-bit
+// windows (d <= 1) for M < 2^48.
 
 // One Newton step toward 1/m from r: relative error e becomes e^2 + 2^-53.
 // From 1/(M - 2a), at most 2^-26.6 away for M >= 2^31 and a <= 10, one step

@@ -83,11 +83,17 @@ constexpr uint32_t kNoQuery = 0xffffffffu;
 // another query first flushes them into that query's carry-save counters with
 // 2L atomics. The counters stay exact while fewer than 2^32 chunks of one
 // query are added up, which the host guarantees.
+//
+// Thread 0 also claims the workgroup's next chunk from the launch's counter
+// (chunks 0 .. grid-1 are taken first, by block index); the fold's barriers
+// publish it in *next. It is written after the first barrier, so every
+// thread has read the previous value by then.
 template <int L>
 __device__ __forceinline__ void wg_fold(const uint64_t (&v)[L], uint32_t (*red)[256],
                                         unsigned long long *sums, unsigned long long *pend,
                                         uint32_t *pend_off, uint32_t acc_off,
-                                        unsigned long long *acc) {
+                                        unsigned long long *acc, unsigned long long *ctr,
+                                        unsigned long long *next) {
   const uint32_t tid = threadIdx.x;
 #pragma unroll
   for (int i = 0; i < L; ++i) {
@@ -102,6 +108,7 @@ __device__ __forceinline__ void wg_fold(const uint64_t (&v)[L], uint32_t (*red)[
   }
   __syncthreads();
   if (tid == 0) {
+    *next = gridDim.x + atomicAdd(ctr, 1ull);
     unsigned long long carry = 0;
     for (int h = 0; h < 2 * L; ++h) {
       const unsigned long long x = sums[h] + carry;
@@ -203,17 +210,21 @@ __device__ __forceinline__ void lane_run62(uint64_t k0, uint32_t run, uint32_t p
   }
 }
 
-// Binary64 terms of one lane, 2^31 <= M < 2^48 (W = 2 for M < 2^46, else
-// W = 1): s = 2^X mod M with X = E + 64L by a left-to-right ladder over
-// W-bit windows (W squarings, the window's value folded into the last one as
-// a power of two). The top t <= 6 bits v of X give the start 2^v mod M
-// directly; t is chosen so that the remaining bit count is a multiple of W,
-// which also keeps every two-bit window inside one 32-bit half of X. The
-// reciprocal of each modulus comes from the previous one by a Newton step.
+// Binary64 terms of one lane, 2^31 <= M < 2^48: s = 2^X mod M with
+// X = E + 64L by a left-to-right ladder over W-bit windows (W squarings, the
+// window's value folded into the last one as a power of two); W = 3 for
+// M < 2^42, 2 for M < 2^46, else 1. The top t = min(6, bitlen X) bits v of X
+// give the start 2^v mod M directly; the remaining bits begin with one short
+// window (their count mod W) and then whole windows at multiples of W. The
+// whole windows above bit S = 32 - (32 mod W) are read from X >> S and the
+// rest from the low word, so none straddles two words. The reciprocal of
+// each modulus comes from the previous one by a Newton step.
 template <int L, int W>
 __device__ __forceinline__ void lane_runf(uint64_t k0, uint32_t run, uint64_t kend, uint64_t a,
                                           uint64_t b, uint64_t dc, uint64_t step, uint32_t P,
                                           uint64_t (&sum)[L]) {
+  constexpr int S = 32 - 32 % W;
+  constexpr uint32_t kDigit = (1u << W) - 1u;
   const uint64_t dM = 2u * a, dX = 2u * step;
   uint64_t M = a * k0 + b;
   uint64_t X = dc + 64ull * L - step * k0;
@@ -226,27 +237,23 @@ __device__ __forceinline__ void lane_runf(uint64_t k0, uint32_t run, uint64_t ke
     const uint64_t k = k0 + 2ull * i;
     if (uniform64(k) >= kend) break;
     const int nb = bitlen64(uniform64(X));
-    int tb;
-    if (W == 2)
-      tb = nb <= 6 ? nb : 6 - ((nb - 6) & 1);
-    else
-      tb = nb < 6 ? nb : 6;
-    const int rest = nb - tb;
+    const int rest = nb < 6 ? 0 : nb - 6;
+    const int lead = rest % W, top = rest - lead;
     double x = pow2_f64((uint32_t)(X >> rest), Md, inv);
-    const uint32_t xl = (uint32_t)X, xh = (uint32_t)(X >> 32);
-    if (W == 2) {
-      for (int p = rest - 2; p >= 32; p -= 2) {
-        x = sqr_f64(x, Md, inv);
-        x = sqr_f64(x, (int)((xh >> (p - 32)) & 3u), Md, inv);
-      }
-      for (int p = (rest < 32 ? rest : 32) - 2; p >= 0; p -= 2) {
-        x = sqr_f64(x, Md, inv);
-        x = sqr_f64(x, (int)((xl >> p) & 3u), Md, inv);
-      }
-    } else {
-      for (int p = rest - 1; p >= 32; --p) x = sqr_f64(x, (int)((xh >> (p - 32)) & 1u), Md, inv);
-      for (int p = (rest < 32 ? rest : 32) - 1; p >= 0; --p)
-        x = sqr_f64(x, (int)((xl >> p) & 1u), Md, inv);
+    if (lead) {
+      for (int j = 1; j < lead; ++j) x = sqr_f64(x, Md, inv);
+      x = sqr_f64(x, (int)((uint32_t)(X >> top) & ((1u << lead) - 1u)), Md, inv);
+    }
+    const uint32_t xhi = (uint32_t)(X >> S), xlo = (uint32_t)X;
+    for (int p = top - W; p >= S; p -= W) {
+#pragma unroll
+      for (int j = 1; j < W; ++j) x = sqr_f64(x, Md, inv);
+      x = sqr_f64(x, (int)((xhi >> (p - S)) & kDigit), Md, inv);
+    }
+    for (int p = (top < S ? top : S) - W; p >= 0; p -= W) {
+#pragma unroll
+      for (int j = 1; j < W; ++j) x = sqr_f64(x, Md, inv);
+      x = sqr_f64(x, (int)((xlo >> p) & kDigit), Md, inv);
     }
     const uint64_t sres = residue_u64(x, Md);  // == 2^(E + 64L) (mod M), in [0, M)
     uint64_t t[L];
@@ -308,18 +315,21 @@ __device__ __forceinline__ void lane_run32(uint64_t k0, uint32_t run, uint64_t k
   }
 }
 
+// Chunks are handed out dynamically: each workgroup starts at its block
+// index and then takes the next unclaimed chunk from *ctr (zero at launch),
+// so workgroups that draw cheap chunks keep working until the last one.
 template <int L>
 __device__ void head_chunks(const HeadSeg *segs, int nseg, uint64_t nchunks,
-                            unsigned long long *acc) {
+                            unsigned long long *acc, unsigned long long *ctr) {
   __shared__ uint32_t red[2 * L][256];
-  __shared__ unsigned long long sums[2 * L], pend[2 * L];
+  __shared__ unsigned long long sums[2 * L], pend[2 * L], next;
   __shared__ uint32_t pend_off;
   const uint32_t tid = threadIdx.x;
   const uint32_t pair = tid >> 1, par = tid & 1u;
   if (tid < 2u * L) pend[tid] = 0;
   if (tid == 0) pend_off = kNoQuery;
   __syncthreads();
-  for (uint64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+  for (uint64_t ch = blockIdx.x; ch < nchunks; ch = next) {
     const HeadSeg sg = find_seg(segs, nseg, ch);
     const uint32_t run = sg.run;
     const uint64_t CH = 256ull * run;
@@ -338,26 +348,29 @@ __device__ void head_chunks(const HeadSeg *segs, int nseg, uint64_t nchunks,
       case 64: lane_run62<L>(k0, run, sg.pre, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
       case 48: lane_runf<L, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
       case 46: lane_runf<L, 2>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+      case 42: lane_runf<L, 3>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
       case 31: lane_run32<L, false, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
       case 29: lane_run32<L, true, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
       default: lane_run32<L, true, false>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
     }
     if (neg) neg_limbs<L>(sum);
-    wg_fold<L>(sum, red, sums, pend, &pend_off, sg.acc_off, acc);
+    wg_fold<L>(sum, red, sums, pend, &pend_off, sg.acc_off, acc, ctr, &next);
   }
   wg_flush<L>(pend, &pend_off, acc);
 }
 
 template <int L>
 __global__ __launch_bounds__(256) void head_kernel_args(HeadSegTable tab, uint64_t nchunks,
-                                                        unsigned long long *acc) {
-  head_chunks<L>(tab.s, tab.n, nchunks, acc);
+                                                        unsigned long long *acc,
+                                                        unsigned long long *ctr) {
+  head_chunks<L>(tab.s, tab.n, nchunks, acc, ctr);
 }
 
 template <int L>
 __global__ __launch_bounds__(256) void head_kernel_ptr(const HeadSeg *segs, int nseg,
-                                                       uint64_t nchunks, unsigned long long *acc) {
-  head_chunks<L>(segs, nseg, nchunks, acc);
+                                                       uint64_t nchunks, unsigned long long *acc,
+                                                       unsigned long long *ctr) {
+  head_chunks<L>(segs, nseg, nchunks, acc, ctr);
 }
 
 __global__ void zero_kernel(unsigned long long *p, uint64_t n) {
@@ -551,14 +564,17 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinQuery single, const Fi
 
 template <int L>
 static hipError_t launch_head_args_L(const HeadSegTable &tab, uint64_t nchunks, int grid,
-                                     unsigned long long *acc, hipStream_t st) {
-  hipLaunchKernelGGL(head_kernel_args<L>, dim3(grid), dim3(256), 0, st, tab, nchunks, acc);
+                                     unsigned long long *acc, unsigned long long *ctr,
+                                     hipStream_t st) {
+  hipLaunchKernelGGL(head_kernel_args<L>, dim3(grid), dim3(256), 0, st, tab, nchunks, acc, ctr);
   return hipGetLastError();
 }
 template <int L>
 static hipError_t launch_head_ptr_L(const HeadSeg *segs, int nseg, uint64_t nchunks, int grid,
-                                    unsigned long long *acc, hipStream_t st) {
-  hipLaunchKernelGGL(head_kernel_ptr<L>, dim3(grid), dim3(256), 0, st, segs, nseg, nchunks, acc);
+                                    unsigned long long *acc, unsigned long long *ctr,
+                                    hipStream_t st) {
+  hipLaunchKernelGGL(head_kernel_ptr<L>, dim3(grid), dim3(256), 0, st, segs, nseg, nchunks, acc,
+                     ctr);
   return hipGetLastError();
 }
 template <int L>
@@ -584,14 +600,14 @@ static hipError_t launch_fin_L(const FinQuery &single, const FinQuery *qs, int n
   }
 
 hipError_t launch_head_args(int Lk, const HeadSegTable &tab, uint64_t nchunks, int grid,
-                            unsigned long long *acc, hipStream_t st) {
-#define C(L) launch_head_args_L<L>(tab, nchunks, grid, acc, st)
+                            unsigned long long *acc, unsigned long long *ctr, hipStream_t st) {
+#define C(L) launch_head_args_L<L>(tab, nchunks, grid, acc, ctr, st)
   PIBBP_DISPATCH(Lk, C)
 #undef C
 }
 hipError_t launch_head_ptr(int Lk, const HeadSeg *segs, int nseg, uint64_t nchunks, int grid,
-                           unsigned long long *acc, hipStream_t st) {
-#define C(L) launch_head_ptr_L<L>(segs, nseg, nchunks, grid, acc, st)
+                           unsigned long long *acc, unsigned long long *ctr, hipStream_t st) {
+#define C(L) launch_head_ptr_L<L>(segs, nseg, nchunks, grid, acc, ctr, st)
   PIBBP_DISPATCH(Lk, C)
 #undef C
 }

@@ -8,7 +8,7 @@
 namespace pibbp {
 
 constexpr int PI_MAX_L = 17;          // ceil(PI_MAX_P / 64)
-constexpr int kMaxArgSegs = 42;       // 7 series x 6 modulus ranges
+constexpr int kMaxArgSegs = 49;       // 7 series x 7 modulus ranges
 
 // A range [kb, ke) of head indices (E >= 0) of series j of one query, all of
 // one modulus class; its chunks are numbered chunk0, chunk0 + 1, ...
@@ -45,10 +45,12 @@ struct FinQuery {
   uint32_t pad;
 };
 
+// Head launches: `ctr` is one device word that must be zero when the launch
+// starts (the dynamic chunk counter); the launch leaves it nonzero.
 hipError_t launch_head_args(int Lk, const HeadSegTable &tab, uint64_t nchunks, int grid,
-                            unsigned long long *acc, hipStream_t st);
+                            unsigned long long *acc, unsigned long long *ctr, hipStream_t st);
 hipError_t launch_head_ptr(int Lk, const HeadSeg *segs, int nseg, uint64_t nchunks, int grid,
-                           unsigned long long *acc, hipStream_t st);
+                           unsigned long long *acc, unsigned long long *ctr, hipStream_t st);
 hipError_t launch_finalize(int Lk, const FinQuery &single, const FinQuery *qs, int nq,
                            const unsigned long long *acc, uint64_t *out, pi_status *status,
                            hipStream_t st);

@@ -27,6 +27,7 @@ using namespace pibbp::host;
 namespace {
 
 constexpr uint32_t kSlotCounters = 2u * PI_MAX_L;  // carry-save counters per slot
+constexpr uint32_t kChunkCounters = 16;             // one per head launch of a step (<= 9)
 
 struct Active {
   uint64_t tag = 0;
@@ -49,7 +50,7 @@ struct pi_server {
   hipStream_t st = nullptr;
   uint32_t cap = 0;
   uint64_t step_terms = 0;
-  unsigned long long *acc = nullptr;  // cap x kSlotCounters
+  unsigned long long *acc = nullptr;  // cap x kSlotCounters, then kChunkCounters
   uint64_t *res = nullptr;            // cap x PI_MAX_L limbs, rows in finish order
   pi_status *res_st = nullptr;        // cap
   HeadSeg *dsegs = nullptr;
@@ -111,7 +112,7 @@ int pi_server_create(uint32_t max_active, uint64_t step_terms, hipStream_t strea
   // device bytes one slot can need: counters, result row and status, and its
   // share of the step tables (up to 35 segments and one finalize record)
   const size_t per_slot = kSlotCounters * 8u + PI_MAX_L * 8u + sizeof(pi_status) +
-                          35u * sizeof(HeadSeg) + sizeof(FinQuery);
+                          kMaxArgSegs * sizeof(HeadSeg) + sizeof(FinQuery);
   const uint64_t by_mem = (uint64_t)(free_b / 4u / per_slot);
   const uint32_t cap = (uint32_t)std::min<uint64_t>(max_active, by_mem);
   if (cap == 0) return PI_ENOMEM;
@@ -119,7 +120,8 @@ int pi_server_create(uint32_t max_active, uint64_t step_terms, hipStream_t strea
   s->st = stream;
   s->cap = cap;
   s->step_terms = step_terms;
-  if (hipMalloc((void **)&s->acc, (size_t)cap * kSlotCounters * 8u) != hipSuccess ||
+  if (hipMalloc((void **)&s->acc, ((size_t)cap * kSlotCounters + kChunkCounters) * 8u) !=
+          hipSuccess ||
       hipMalloc((void **)&s->res, (size_t)cap * PI_MAX_L * 8u) != hipSuccess ||
       hipMalloc((void **)&s->res_st, (size_t)cap * sizeof(pi_status)) != hipSuccess) {
     release(s);
@@ -217,14 +219,19 @@ int pi_server_step(pi_server *s, uint32_t *finished) {
   if (nfins && hipMemcpyAsync(s->dfins, fhost, nfins * sizeof(FinQuery), hipMemcpyHostToDevice,
                               s->st) != hipSuccess)
     return PI_EDEVICE;
-  // 4. head launches, then finalize launches, per limb class
+  // 4. head launches (each with its own chunk counter, cleared first), then
+  //    finalize launches, per limb class
+  unsigned long long *ctr = s->acc + (uint64_t)s->cap * kSlotCounters;
+  if (!seg_at.empty())
+    if (int e = hip_err(launch_zero(ctr, kChunkCounters, s->st))) return e;
+  int launch = 0;
   for (auto &kv : seg_at) {
     const int Lk = kv.first;
     const uint64_t nch = chunks_by_class[Lk];
     if (!nch) continue;
     const int grid = (int)std::min<uint64_t>(nch, (uint64_t)resident_grid(Lk));
     if (int e = hip_err(launch_head_ptr(Lk, s->dsegs + kv.second.first, (int)kv.second.second, nch,
-                                        grid, s->acc, s->st)))
+                                        grid, s->acc, ctr + launch++, s->st)))
       return e;
   }
   FinQuery none;
