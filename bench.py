@@ -30,11 +30,13 @@ sys.path.insert(0, ROOT)
 PEAK_VALU = 256 * 64 * 2.4e9
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "head_kernel_bellard_n1e12_P320_traffic.json")
-KERNEL_SOURCES = ["kernels.hip", "arith.h", "plan.h"]
+# the head kernel's device code and the planner that sizes its chunks (the
+# chunk count sets the scheduler's atomics, hence the write traffic)
+KERNEL_SOURCES = ["kernels.hip", "arith.h", "plan.h", "abi.cpp", "host.h"]
 
 
 def kernel_source_hash():
-    """sha256 over the device sources of the head kernel."""
+    """sha256 over the sources of the head kernel and its launch planning."""
     import hashlib
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
@@ -86,8 +88,9 @@ def _pre_bits(run, Mmin, Mmax, a):
 # compiled gfx950 code (loop control and scheduling excluded):
 #  * binary64 classes (2^31 <= M < 2^48, windows of W = 3, 2, 1 bits): the
 #    top 6 bits of X = E + 64L are the start value; each remaining bit costs
-#    a squaring (6 instructions), each whole window 2 more (exponent digit,
-#    scale) and a short leading window 3 more; 100 per term for the start,
+#    a squaring (6 instructions, 9 with the second reduction from 2^48), each
+#    whole window 2 more (exponent digit, scale) and a short leading window 3
+#    more; about 100 per term for the start,
 #    reciprocal, residue, 32-bit inverse, the ten-digit Hensel division at
 #    L = 5, the mask and the accumulation;
 #  * integer classes (Montgomery): a fixed cost per ladder bit of
@@ -100,7 +103,8 @@ KERNEL_CLASSES = [
     ("f3", 2 ** 31, 3, 6, 100, 0),    # binary64, three-bit windows
     ("f2", 2 ** 42, 2, 6, 100, 0),    # binary64, two-bit windows
     ("f1", 2 ** 46, 1, 6, 101, 0),    # binary64, one-bit windows
-    ("62", 2 ** 48, 1, 16, 116, -62), # R = 2^62, two 31-bit digits
+    ("fr", 2 ** 48, 2, 9, 100, 0),    # binary64, two-bit windows, re-reduced
+    ("62", 2 ** 51, 1, 16, 116, -62), # R = 2^62, two 31-bit digits
 ]
 
 

@@ -53,9 +53,9 @@ def tune(classes=None, log=sys.stdout):
     result = {"arch": arch, "classes": {}}
     for L in classes:
         spec = WORKLOADS[L]
-        pb.set_tuning(L, 0, 64)
+        pb.set_tuning(L, 0, 256)
         base_ms, ref = time_one(pb, torch, spec)
-        best = (base_ms, 0, 64)
+        best = (base_ms, 0, 256)
         for wg in WG_PER_CU:
             for cap in RUN_CAPS:
                 pb.set_tuning(L, wg, cap)

@@ -17,11 +17,12 @@
 //
 // Modulus classes keep the instruction count down:
 //  * class 32 (M < 2^31): R = 2^32, residues kept below M;
-//  * binary64 (2^31 <= M < 2^48): plain (not Montgomery) residues held
+//  * binary64 (2^31 <= M < 2^51): plain (not Montgomery) residues held
 //    exactly in doubles; a squaring is six full-rate fp64 instructions
-//    against sixteen integer ones for the same modulus in class 62, and
-//    exponent windows of up to three bits cost one more per window;
-//  * class 62 (2^48 <= M < 2^54): R = 2^62, residues in two 31-bit digits,
+//    against sixteen integer ones for the same modulus in class 62 (nine
+//    from 2^48, with a second reduction), and exponent windows of up to
+//    three bits cost one more per window;
+//  * class 62 (2^51 <= M < 2^54): R = 2^62, residues in two 31-bit digits,
 //    kept below 8M;
 //  * R = 2^64 with residues below 2M (M < 2^60): the few tail terms.
 // v_mad_u64_u32 issues at full rate on gfx950, so the integer classes are
@@ -32,7 +33,7 @@
 
 namespace pibbp {
 
-// ---- binary64 residues, 2^31 <= M < 2^48 -----------------------------------
+// ---- binary64 residues, 2^31 <= M < 2^51 -----------------------------------
 //
 // A residue is an integer-valued double x with |x| < M (signed, not reduced).
 // One step computes y = 2^d x^2 - qM:
@@ -75,6 +76,16 @@ __device__ __forceinline__ double sqr_f64(double x, double M, double inv) {
   const double lo = __builtin_fma(x, x, -h);
   const double q = __builtin_rint(h * inv);
   return __builtin_fma(-q, M, h) + lo;
+}
+
+// For 2^48 <= M < 2^51 each squaring is followed by r - rint(r * inv) M,
+// three more instructions that bring any |r| < 2^53 back to |r| <= M/2 + 1.
+// From |x| <= 0.51 M and d <= 3, H <= 2.08 M^2, so the first stage's
+// remainder is at most M/2 + 2^-51 H < 2.6 M < 2^53 and stays exact.
+__device__ __forceinline__ double rereduce_f64(double r, double M, double inv) {
+#pragma clang fp contract(off)
+  const double q = __builtin_rint(r * inv);
+  return __builtin_fma(-q, M, r);
 }
 
 // 2^v mod M, |result| < M, for v < 64 and M >= 2^31: the error term

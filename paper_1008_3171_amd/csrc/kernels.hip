@@ -210,16 +210,17 @@ __device__ __forceinline__ void lane_run62(uint64_t k0, uint32_t run, uint32_t p
   }
 }
 
-// Binary64 terms of one lane, 2^31 <= M < 2^48: s = 2^X mod M with
+// Binary64 terms of one lane, 2^31 <= M < 2^51: s = 2^X mod M with
 // X = E + 64L by a left-to-right ladder over W-bit windows (W squarings, the
 // window's value folded into the last one as a power of two); W = 3 for
-// M < 2^42, 2 for M < 2^46, else 1. The top t = min(6, bitlen X) bits v of X
+// M < 2^42, 2 for M < 2^46, 1 for M < 2^48, and from there W = 2 with a
+// second reduction after every squaring (kRe). The top t = min(6, bitlen X) bits v of X
 // give the start 2^v mod M directly; the remaining bits begin with one short
 // window (their count mod W) and then whole windows at multiples of W. The
 // whole windows above bit S = 32 - (32 mod W) are read from X >> S and the
 // rest from the low word, so none straddles two words. The reciprocal of
 // each modulus comes from the previous one by a Newton step.
-template <int L, int W>
+template <int L, int W, bool kRe>
 __device__ __forceinline__ void lane_runf(uint64_t k0, uint32_t run, uint64_t kend, uint64_t a,
                                           uint64_t b, uint64_t dc, uint64_t step, uint32_t P,
                                           uint64_t (&sum)[L]) {
@@ -240,20 +241,28 @@ __device__ __forceinline__ void lane_runf(uint64_t k0, uint32_t run, uint64_t ke
     const int rest = nb < 6 ? 0 : nb - 6;
     const int lead = rest % W, top = rest - lead;
     double x = pow2_f64((uint32_t)(X >> rest), Md, inv);
+    auto sq = [&](double y) {
+      y = sqr_f64(y, Md, inv);
+      return kRe ? rereduce_f64(y, Md, inv) : y;
+    };
+    auto sqd = [&](double y, uint32_t dg) {
+      y = sqr_f64(y, (int)dg, Md, inv);
+      return kRe ? rereduce_f64(y, Md, inv) : y;
+    };
     if (lead) {
-      for (int j = 1; j < lead; ++j) x = sqr_f64(x, Md, inv);
-      x = sqr_f64(x, (int)((uint32_t)(X >> top) & ((1u << lead) - 1u)), Md, inv);
+      for (int j = 1; j < lead; ++j) x = sq(x);
+      x = sqd(x, (uint32_t)(X >> top) & ((1u << lead) - 1u));
     }
     const uint32_t xhi = (uint32_t)(X >> S), xlo = (uint32_t)X;
     for (int p = top - W; p >= S; p -= W) {
 #pragma unroll
-      for (int j = 1; j < W; ++j) x = sqr_f64(x, Md, inv);
-      x = sqr_f64(x, (int)((xhi >> (p - S)) & kDigit), Md, inv);
+      for (int j = 1; j < W; ++j) x = sq(x);
+      x = sqd(x, (xhi >> (p - S)) & kDigit);
     }
     for (int p = (top < S ? top : S) - W; p >= 0; p -= W) {
 #pragma unroll
-      for (int j = 1; j < W; ++j) x = sqr_f64(x, Md, inv);
-      x = sqr_f64(x, (int)((xlo >> p) & kDigit), Md, inv);
+      for (int j = 1; j < W; ++j) x = sq(x);
+      x = sqd(x, (xlo >> p) & kDigit);
     }
     const uint64_t sres = residue_u64(x, Md);  // == 2^(E + 64L) (mod M), in [0, M)
     uint64_t t[L];
@@ -346,9 +355,10 @@ __device__ void head_chunks(const HeadSeg *segs, int nseg, uint64_t nchunks,
     for (int i = 0; i < L; ++i) sum[i] = 0;
     switch (sg.cls) {
       case 64: lane_run62<L>(k0, run, sg.pre, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
-      case 48: lane_runf<L, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
-      case 46: lane_runf<L, 2>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
-      case 42: lane_runf<L, 3>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+      case 51: lane_runf<L, 2, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+      case 48: lane_runf<L, 1, false>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+      case 46: lane_runf<L, 2, false>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+      case 42: lane_runf<L, 3, false>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
       case 31: lane_run32<L, false, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
       case 29: lane_run32<L, true, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
       default: lane_run32<L, true, false>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;

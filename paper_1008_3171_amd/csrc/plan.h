@@ -8,7 +8,7 @@
 namespace pibbp {
 
 constexpr int PI_MAX_L = 17;          // ceil(PI_MAX_P / 64)
-constexpr int kMaxArgSegs = 49;       // 7 series x 7 modulus ranges
+constexpr int kMaxArgSegs = 56;       // 7 series x 8 modulus ranges
 
 // A range [kb, ke) of head indices (E >= 0) of series j of one query, all of
 // one modulus class; its chunks are numbered chunk0, chunk0 + 1, ...
@@ -16,13 +16,16 @@ struct HeadSeg {
   uint64_t kb, ke;
   uint64_t chunk0;
   uint64_t d;          // n - 1
-  uint32_t formula, j, P;
+  uint32_t P;
   uint32_t acc_off;    // the query's carry-save counters: acc + acc_off
-  uint32_t cls;        // R = 2^32: 22 (M < 2^22), 29 (< 2^29), 31 (< 2^31); 64: R = 2^62, M < 2^54
   uint32_t run;        // indices per lane per chunk; a chunk is 256 * run indices
-  uint32_t pre;        // class 62: exponent bits taken into the ladder's start value
-  uint32_t pad;
+  uint8_t formula, j;
+  uint8_t cls;         // arithmetic by modulus: R = 2^32 Montgomery 22 (M < 2^22),
+                       // 29 (< 2^29), 31 (< 2^31); binary64 42 (< 2^42), 46 (< 2^46),
+                       // 48 (< 2^48), 51 (< 2^51); 64: R = 2^62 Montgomery (M < 2^54)
+  uint8_t pre;         // class 62: exponent bits taken into the ladder's start value
 };
+static_assert(sizeof(HeadSeg) == 48, "HeadSeg layout");
 
 // Segments of a single query, passed by value as a kernel argument.
 struct HeadSegTable {
