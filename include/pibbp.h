@@ -12,8 +12,9 @@
  * and a division; the B_k of eq (3.3) when E < 0) and adds
  * sign_j * alt^k * t_{j,k} modulo 2^P. Formulas: Bellard's (eq (1.2); step
  * 10, alternating signs, seven series) and the BBP formula (eq (1.1), in the
- * odd-denominator form of eq (3.1); step 4, four series). Everything is exact
- * integer arithmetic; there is no floating point.
+ * odd-denominator form of eq (3.1); step 4, four series). Every result is
+ * exact: integer arithmetic, plus binary64 operations on integer-valued
+ * doubles that are proven never to round.
  *
  * Conventions shared by every call:
  *  - n is the 1-based position of the first result bit after the radix point

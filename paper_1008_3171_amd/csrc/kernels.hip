@@ -1,12 +1,13 @@
 // Kernels of the MI355X bit-extraction library.
 //
 //  head_kernel<L, ...>  the hot path: every head term (E >= 0, the A_k of
-//                       eq (3.3)) of every series range it is given. One
-//                       workgroup takes a chunk of 256*run consecutive k of
-//                       one series; each lane owns run indices of one parity
-//                       (so one sign), sums its terms, and the workgroup
-//                       folds the 256 lane sums into carry-save counters of
-//                       its query with 2L atomics.
+//                       eq (3.3)) of every series range it is given. A
+//                       resident grid takes chunks of 256*run consecutive k
+//                       of one series from a device counter; each lane owns
+//                       run indices of one parity (so one sign) and sums its
+//                       terms, and the workgroup folds the 256 lane sums into
+//                       pending column sums that reach the query's
+//                       carry-save counters with 2L atomics.
 //  finalize_kernel<L>   one workgroup per query: the tail terms (the B_k of
 //                       eq (3.3)) up to each series' stop index, the
 //                       normalization of the carry-save counters, the
@@ -44,8 +45,9 @@ __constant__ int32_t kNumSeries[2] = {4, 7};
 
 // ---- one term --------------------------------------------------------------
 
-// Head term at L limbs for a class-64 modulus: t = floor(r 2^(64L) / M) with
-// r = 2^E mod M, low bits above P cleared. nb >= bit length of
+// One term at L limbs by the R = 2^64 Montgomery ladder (any odd M < 2^60):
+// t = floor(r 2^(64L) / M) with r = 2^E mod M, low bits below P cleared. The
+// tail uses it with E = 0 for floor(2^(64L) / M). nb >= bit length of
 // X = E + 64(L-1); extra leading zero bits only square the Montgomery one.
 template <int L>
 __device__ __forceinline__ void head_term64(uint64_t E, uint64_t M, uint32_t P, int nb,
@@ -56,18 +58,6 @@ __device__ __forceinline__ void head_term64(uint64_t E, uint64_t M, uint32_t P, 
   for (int j = nb - 1; j >= 0; --j) x = sqr_redc64(x, (uint32_t)(X >> j) & 1u, M, mp);
   x = x >= M ? x - M : x;  // s = 2^(E + 64L) mod M
   hensel64<L>(x, M, mp, t);
-  clip_low<L>(t, P);
-}
-
-// Head term for a class-32 modulus (3 <= M < 2^31); X = E + 64L - 32.
-template <int L>
-__device__ __forceinline__ void head_term32(uint64_t E, uint32_t M, uint32_t P, int nb,
-                                            uint64_t (&t)[L]) {
-  const uint32_t mp = neg_inv32(M);
-  uint32_t x = mont_one32(M);
-  const uint64_t X = E + 64ull * L - 32ull;
-  for (int j = nb - 1; j >= 0; --j) x = sqr_redc32(x, (uint32_t)(X >> j) & 1u, M, mp);
-  hensel32<L>(x, M, mp, t);
   clip_low<L>(t, P);
 }
 

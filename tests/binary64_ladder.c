@@ -1,0 +1,88 @@
+/* CPU model of the head kernel's binary64 modular squaring, for checking its
+ * exactness bounds (test infrastructure; not part of the library).
+ *
+ * A residue is an integer-valued double |x| < M. One step forms
+ * y = 2^d x^2 - qM as the kernel does: H = x * (2^d x) rounded,
+ * Lo = fma(x, 2^d x, -H), q = rint(H * inv), y = fma(-q, M, H) + Lo, and for
+ * moduli from 2^48 a second reduction y - rint(y * inv) M.
+ *
+ * Reads lines "M d x re inv_mode" on stdin (inv_mode 0: inv = 1/M correctly
+ * rounded; 1: one Newton step from 1/(M - 20), as after the previous modulus
+ * of a lane with a = 10) and prints "y ok" per line, where ok is 1 when both
+ * intermediate results were below 2^53 in magnitude (so exact) and |y| < M.
+ * Also answers "L M X W re" lines with the full ladder's 2^X mod M.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+static double newton(double m, double r) {
+  const double e = fma(-m, r, 1.0);
+  return fma(r, e, r);
+}
+
+static double inverse(double M, int mode) {
+  if (mode == 0) return 1.0 / M;
+  return newton(M, 1.0 / (M - 20.0));
+}
+
+static int step(double x, int d, double M, double inv, int re, double *out) {
+  const double xs = ldexp(x, d);
+  const double h = x * xs;
+  const double lo = fma(x, xs, -h);
+  const double q = rint(h * inv);
+  const double r0 = fma(-q, M, h);
+  double y = r0 + lo;
+  int ok = fabs(r0) < 0x1p53 && fabs(y) < 0x1p53;
+  if (re) y = fma(-rint(y * inv), M, y);
+  *out = y;
+  return ok && fabs(y) < M;
+}
+
+/* 2^X mod M by the kernel's ladder: start 2^v for the top 6 bits, one short
+ * window, then W-bit windows; returns the residue in [0, M) or -1. */
+static long long ladder(unsigned long long M, unsigned long long X, int W, int re) {
+  const double Md = (double)M, inv = inverse(Md, 1);
+  const int nb = X ? 64 - __builtin_clzll(X) : 0;
+  const int rest = nb < 6 ? 0 : nb - 6;
+  const int lead = rest % W, top = rest - lead;
+  const double p = ldexp(1.0, (int)(X >> rest));
+  double x = fma(-rint(p * inv), Md, p);
+  if (fabs(x) >= Md) return -1;
+  if (lead) {
+    for (int j = 1; j < lead; ++j)
+      if (!step(x, 0, Md, inv, re, &x)) return -1;
+    if (!step(x, (int)((X >> top) & ((1u << lead) - 1u)), Md, inv, re, &x)) return -1;
+  }
+  for (int q = top - W; q >= 0; q -= W) {
+    for (int j = 1; j < W; ++j)
+      if (!step(x, 0, Md, inv, re, &x)) return -1;
+    if (!step(x, (int)((X >> q) & ((1u << W) - 1u)), Md, inv, re, &x)) return -1;
+  }
+  if (x < 0) x += Md;
+  double y = x + 0x1p52;
+  unsigned long long u;
+  memcpy(&u, &y, 8);
+  return (long long)(u & ((1ull << 52) - 1u));
+}
+
+int main(void) {
+  char kind[8];
+  while (scanf("%7s", kind) == 1) {
+    if (kind[0] == 'S') {
+      double M, x;
+      int d, re, mode;
+      if (scanf("%lf %d %lf %d %d", &M, &d, &x, &re, &mode) != 5) return 1;
+      double y;
+      const int ok = step(x, d, M, inverse(M, mode), re, &y);
+      printf("%.0f %d\n", y, ok);
+    } else {
+      unsigned long long M, X;
+      int W, re;
+      if (scanf("%llu %llu %d %d", &M, &X, &W, &re) != 4) return 1;
+      printf("%lld\n", ladder(M, X, W, re));
+    }
+  }
+  return 0;
+}
