@@ -90,7 +90,7 @@ def _pre_bits(run, Mmin, Mmax, a):
 #    top 6 bits of X = E + 64L are the start value; each remaining bit costs
 #    a squaring (6 instructions, 9 with the second reduction from 2^48), each
 #    whole window 2 more (exponent digit, scale) and a short leading window 3
-#    more; about 100 per term for the start,
+#    more; about 86 per term for the start,
 #    reciprocal, residue, 32-bit inverse, the ten-digit Hensel division at
 #    L = 5, the mask and the accumulation;
 #  * integer classes (Montgomery): a fixed cost per ladder bit of
@@ -100,11 +100,11 @@ KERNEL_CLASSES = [
     ("22", 0, 1, 5, 77, -32),         # R = 2^32, lazy, start by doublings
     ("29", 2 ** 22, 1, 5, 71, -32),   # R = 2^32, lazy, run-quotient start
     ("31", 2 ** 29, 1, 7, 71, -32),   # R = 2^32, reduced residues
-    ("f3", 2 ** 31, 3, 6, 100, 0),    # binary64, three-bit windows
-    ("f2", 2 ** 42, 2, 6, 100, 0),    # binary64, two-bit windows
-    ("f1", 2 ** 46, 1, 6, 101, 0),    # binary64, one-bit windows
-    ("fr", 2 ** 48, 2, 9, 100, 0),    # binary64, two-bit windows, re-reduced
-    ("62", 2 ** 51, 1, 16, 116, -62), # R = 2^62, two 31-bit digits
+    ("f3", 2 ** 31, 3, 6, 87, 0),    # binary64, three-bit windows
+    ("f2", 2 ** 42, 2, 6, 86, 0),    # binary64, two-bit windows
+    ("f1", 2 ** 46, 1, 6, 86, 0),    # binary64, one-bit windows
+    ("fr", 2 ** 48, 2, 9, 86, 0),    # binary64, two-bit windows, re-reduced
+    ("62", 2 ** 51, 1, 16, 112, -62), # R = 2^62, two 31-bit digits
 ]
 
 

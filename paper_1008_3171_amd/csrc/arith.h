@@ -97,12 +97,15 @@ __device__ __forceinline__ double pow2_f64(uint32_t v, double M, double inv) {
   return __builtin_fma(-q, M, p);
 }
 
-// The residue in [0, M) as an integer: adding 2^52 to an integer-valued
-// double in [0, 2^52) puts the integer in the significand field.
-__device__ __forceinline__ uint64_t residue_u64(double x, double M) {
+// The residue in [0, M) as an integer, for |x| < M < 2^48 or |x| <= M/2 + 1
+// (M < 2^51): x * inv then lies strictly between -1 and 1 even after
+// rounding, so its floor is -1 or 0 and x - floor(x * inv) M is in [0, M).
+// Adding 2^52 to an integer-valued double in [0, 2^52) puts the integer in
+// the significand field.
+__device__ __forceinline__ uint64_t residue_u64(double x, double M, double inv) {
 #pragma clang fp contract(off)
-  const double y = (x < 0.0 ? x + M : x) + 0x1p52;
-  return (uint64_t)__double_as_longlong(y) & ((1ull << 52) - 1u);
+  const double r = __builtin_fma(-__builtin_floor(x * inv), M, x);
+  return (uint64_t)__double_as_longlong(r + 0x1p52) & ((1ull << 52) - 1u);
 }
 
 // -M^-1 mod 2^32, M odd. (3M) xor 2 is an inverse to 5 bits; each Newton step
@@ -312,6 +315,15 @@ __device__ __forceinline__ void hensel64(uint64_t s, uint64_t M, uint64_t mp, ui
   }
 }
 
+// x >> 1 as one 64-bit shift whose low register is then reused as lo32:
+// written out, the compiler recomputes that low word with an extra funnel
+// shift from the unshifted value.
+__device__ __forceinline__ uint64_t shr1_64(uint64_t x) {
+  uint64_t y;
+  asm("v_lshrrev_b64 %0, 1, %1" : "=v"(y) : "v"(x));
+  return y;
+}
+
 // The same quotient from 32-bit digits for any odd M < 2^62, with only
 // mp32 = -M^-1 mod 2^32. Digit u = lo32(h) * mp32 makes h + uM divisible by
 // 2^32. With M = m1 2^31 + m0 (m0 < 2^31): A = u m0 + h stays below 2^64 and
@@ -330,7 +342,7 @@ __device__ __forceinline__ void hensel_d32(uint64_t s, uint64_t M, uint32_t mp32
     for (int j = 0; j < 2; ++j) {
       const uint32_t u = (uint32_t)h * mp32;
       const uint64_t A = mad64(u, m0, h);
-      h = mad64(u, m1, A >> 31) >> 1;
+      h = shr1_64(mad64(u, m1, A >> 31));
       dg[j] = u;
     }
     t[i] = ((uint64_t)dg[1] << 32) | dg[0];

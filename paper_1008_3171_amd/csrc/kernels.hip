@@ -216,7 +216,7 @@ __device__ __forceinline__ void lane_runf(uint64_t k0, uint32_t run, uint64_t ke
                                           uint64_t (&sum)[L]) {
   constexpr int S = 32 - 32 % W;
   constexpr uint32_t kDigit = (1u << W) - 1u;
-  const uint64_t dM = 2u * a, dX = 2u * step;
+  const uint64_t dM = 2u * a, ndX = 0u - 2u * uniform64(step);
   uint64_t M = a * k0 + b;
   uint64_t X = dc + 64ull * L - step * k0;
   double Md = (double)M;
@@ -224,11 +224,16 @@ __device__ __forceinline__ void lane_runf(uint64_t k0, uint32_t run, uint64_t ke
   double inv = recip_f64(Md);
   uint64_t msk[L];
   low_masks<L>(P, msk);
-  for (uint32_t i = 0; i < run; ++i, M += dM, X -= dX) {
-    const uint64_t k = k0 + 2ull * i;
-    if (uniform64(k) >= kend) break;
-    const int nb = bitlen64(uniform64(X));
-    const int rest = nb < 6 ? 0 : nb - 6;
+  // terms of this lane inside the chunk (nv) and of lane 0 (nw: lane 0 has
+  // the wave's smallest k, so the wave stops after nw terms); lane 0's
+  // exponent, the wave's largest, is kept in scalar registers
+  const uint64_t ke = uniform64(kend), kw = uniform64(k0);
+  const uint32_t nv = k0 < ke ? (uint32_t)((ke - k0 + 1u) >> 1) : 0u;
+  const uint32_t nw = kw < ke ? min(run, (uint32_t)((ke - kw + 1u) >> 1)) : 0u;
+  uint64_t Xw = uniform64(X);
+  for (uint32_t i = 0; i < nw; ++i, M += dM, X += ndX, Xw += ndX) {
+    const int nb = bitlen64(Xw);
+    const int rest = max(nb - 6, 0);
     const int lead = rest % W, top = rest - lead;
     double x = pow2_f64((uint32_t)(X >> rest), Md, inv);
     auto sq = [&](double y) {
@@ -254,11 +259,11 @@ __device__ __forceinline__ void lane_runf(uint64_t k0, uint32_t run, uint64_t ke
       for (int j = 1; j < W; ++j) x = sq(x);
       x = sqd(x, (xlo >> p) & kDigit);
     }
-    const uint64_t sres = residue_u64(x, Md);  // == 2^(E + 64L) (mod M), in [0, M)
+    const uint64_t sres = residue_u64(x, Md, inv);  // == 2^(E + 64L) (mod M), in [0, M)
     uint64_t t[L];
     hensel_d32<L>(sres, M, neg_inv32((uint32_t)M), t);
     apply_masks<L>(t, msk);
-    if (k < kend) add_limbs<L>(sum, t);
+    if (i < nv) add_limbs<L>(sum, t);
     Md += dMd;
     inv = recip_step(Md, inv);
   }
