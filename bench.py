@@ -97,14 +97,14 @@ def _pre_bits(run, Mmin, Mmax, a):
 #    X = E + 64L + offset (class 62 folds `pre` top bits into its start).
 #   (name, first modulus, W, per bit, per term, X offset - 64L)
 KERNEL_CLASSES = [
-    ("22", 0, 1, 5, 77, -32),         # R = 2^32, lazy, start by doublings
-    ("29", 2 ** 22, 1, 5, 71, -32),   # R = 2^32, lazy, run-quotient start
-    ("31", 2 ** 29, 1, 7, 71, -32),   # R = 2^32, reduced residues
+    ("22", 0, 1, 5, 73, -32),         # R = 2^32, lazy, start by doublings
+    ("29", 2 ** 22, 1, 5, 67, -32),   # R = 2^32, lazy, run-quotient start
+    ("31", 2 ** 29, 1, 7, 67, -32),   # R = 2^32, reduced residues
     ("f3", 2 ** 31, 3, 6, 87, 0),    # binary64, three-bit windows
     ("f2", 2 ** 42, 2, 6, 86, 0),    # binary64, two-bit windows
     ("f1", 2 ** 46, 1, 6, 86, 0),    # binary64, one-bit windows
     ("fr", 2 ** 48, 2, 9, 86, 0),    # binary64, two-bit windows, re-reduced
-    ("62", 2 ** 51, 1, 16, 112, -62), # R = 2^62, two 31-bit digits
+    ("62", 2 ** 51, 1, 16, 104, -62), # R = 2^62, two 31-bit digits
 ]
 
 

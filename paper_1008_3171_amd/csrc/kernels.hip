@@ -164,18 +164,20 @@ template <int L>
 __device__ __forceinline__ void lane_run62(uint64_t k0, uint32_t run, uint32_t pre, uint64_t kend,
                                            uint64_t a, uint64_t b, uint64_t dc, uint64_t step,
                                            uint32_t P, uint64_t (&sum)[L]) {
-  const uint64_t dM = 2u * a, dX = 2u * step;
+  const uint64_t dM = 2u * a, ndX = 0u - 2u * uniform64(step);
   uint64_t M = a * k0 + b;
   uint64_t X = dc + 64ull * L - 62ull - step * k0;
   const uint32_t q = div_2_62(M + dM * (run - 1u));
   uint64_t msk[L];
   low_masks<L>(P, msk);
-  for (uint32_t i = 0; i < run; ++i, M += dM, X -= dX) {
-    const uint64_t k = k0 + 2ull * i;
-    // lane 0 holds the wave's smallest k, so the largest exponent: if it is
-    // past the chunk, so is every lane, and its X bounds the ladder length.
-    if (uniform64(k) >= kend) break;
-    const int nb0 = bitlen64(uniform64(X));
+  // lane 0 holds the wave's smallest k, so the largest exponent: the wave
+  // runs lane 0's term count nw, and lane 0's X bounds the ladder length
+  const uint64_t ke = uniform64(kend), kw = uniform64(k0);
+  const uint32_t nv = k0 < ke ? (uint32_t)((ke - k0 + 1u) >> 1) : 0u;
+  const uint32_t nw = kw < ke ? min(run, (uint32_t)((ke - kw + 1u) >> 1)) : 0u;
+  uint64_t Xw = uniform64(X);
+  for (uint32_t i = 0; i < nw; ++i, M += dM, X += ndX, Xw += ndX) {
+    const int nb0 = bitlen64(Xw);
     const uint32_t mp32 = neg_inv32((uint32_t)M);
     const uint32_t m0 = (uint32_t)M & kMask31, m1 = (uint32_t)(M >> 31);
     const uint32_t p = mp32 & kMask31;
@@ -196,7 +198,7 @@ __device__ __forceinline__ void lane_run62(uint64_t k0, uint32_t run, uint32_t p
     uint64_t t[L];
     hensel_d32<L>(x, M, mp32, t);
     apply_masks<L>(t, msk);
-    if (k < kend) add_limbs<L>(sum, t);
+    if (i < nv) add_limbs<L>(sum, t);
   }
 }
 
@@ -282,17 +284,19 @@ template <int L, bool kLazy, bool kRunStart>
 __device__ __forceinline__ void lane_run32(uint64_t k0, uint32_t run, uint64_t kend, uint64_t a,
                                            uint64_t b, uint64_t dc, uint64_t step, uint32_t P,
                                            uint64_t (&sum)[L]) {
-  const uint64_t dM = 2u * a, dX = 2u * step;
+  const uint64_t dM = 2u * a, ndX = 0u - 2u * uniform64(step);
   uint64_t M = a * k0 + b;
   uint64_t X = dc + 64ull * L - 32ull - step * k0;
   uint32_t q = 0;
   if (kRunStart) q = div_2_32((uint32_t)(M + dM * (run - 1u)));
   uint64_t msk[L];
   low_masks<L>(P, msk);
-  for (uint32_t i = 0; i < run; ++i, M += dM, X -= dX) {
-    const uint64_t k = k0 + 2ull * i;
-    if (uniform64(k) >= kend) break;
-    const int nb = bitlen64(uniform64(X));
+  const uint64_t ke = uniform64(kend), kw = uniform64(k0);
+  const uint32_t nv = k0 < ke ? (uint32_t)((ke - k0 + 1u) >> 1) : 0u;
+  const uint32_t nw = kw < ke ? min(run, (uint32_t)((ke - kw + 1u) >> 1)) : 0u;
+  uint64_t Xw = uniform64(X);
+  for (uint32_t i = 0; i < nw; ++i, M += dM, X += ndX, Xw += ndX) {
+    const int nb = bitlen64(Xw);
     const uint32_t M32 = (uint32_t)M;
     const uint32_t mp = neg_inv32(M32);
     uint32_t x;
@@ -315,7 +319,7 @@ __device__ __forceinline__ void lane_run32(uint64_t k0, uint32_t run, uint64_t k
     uint64_t t[L];
     hensel32<L>(x, M32, mp, t);
     apply_masks<L>(t, msk);
-    if (k < kend && M != 1) add_limbs<L>(sum, t);
+    if (i < nv && M32 != 1u) add_limbs<L>(sum, t);
   }
 }
 
