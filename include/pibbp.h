@@ -167,9 +167,11 @@ PI_API uint64_t pi_head_terms(int formula, uint64_t n);
 
 /* Launch shape of the head kernel instance for `limbs` = ceil(P/64) rounded
  * up to an instantiated count (1-6, 8, 12, 17), or every instance when limbs
- * is 0: wg_per_cu workgroups per CU (0: as many as fit, from the occupancy
- * API) and run_cap, the most indices one lane takes per chunk. Results do not
- * depend on these; only speed does. The autotuner sets them from its cache. */
+ * is 0: wg_per_cu workgroups per CU (0, the default: as many as fit, from the
+ * occupancy API; at most 64) and run_cap, the most indices one lane takes per
+ * chunk (1..4096, default 256). Results do not depend on these; only speed
+ * does. The autotuner sets them from its cache. PI_EINVAL for limbs outside
+ * 0..17 (1..17 for pi_get_tuning), out-of-range values or NULL outputs. */
 PI_API int pi_set_tuning(int limbs, uint32_t wg_per_cu, uint32_t run_cap);
 PI_API int pi_get_tuning(int limbs, uint32_t *wg_per_cu, uint32_t *run_cap);
 

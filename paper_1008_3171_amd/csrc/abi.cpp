@@ -656,9 +656,10 @@ int pi_extract_batch(const pi_query *q, int count, uint64_t *out, pi_status *sta
 int pi_set_tuning(int limbs, uint32_t wg_per_cu, uint32_t run_cap) {
   if (limbs < 0 || limbs > PI_MAX_L || run_cap == 0 || run_cap > 4096 || wg_per_cu > 64)
     return PI_EINVAL;
+  const int cls = limbs == 0 ? 0 : limb_class(64u * (uint32_t)limbs);
   std::lock_guard<std::mutex> lk(g_mu);
   for (int L = 1; L <= PI_MAX_L; ++L)
-    if (limbs == 0 || L == limbs) {
+    if (cls == 0 || L == cls) {
       g_tune[L].wg_per_cu = wg_per_cu;
       g_tune[L].run_cap = run_cap;
     }
@@ -667,9 +668,10 @@ int pi_set_tuning(int limbs, uint32_t wg_per_cu, uint32_t run_cap) {
 
 int pi_get_tuning(int limbs, uint32_t *wg_per_cu, uint32_t *run_cap) {
   if (limbs < 1 || limbs > PI_MAX_L || !wg_per_cu || !run_cap) return PI_EINVAL;
+  const int cls = limb_class(64u * (uint32_t)limbs);
   std::lock_guard<std::mutex> lk(g_mu);
-  *wg_per_cu = g_tune[limbs].wg_per_cu;
-  *run_cap = g_tune[limbs].run_cap;
+  *wg_per_cu = g_tune[cls].wg_per_cu;
+  *run_cap = g_tune[cls].run_cap;
   return PI_OK;
 }
 

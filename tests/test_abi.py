@@ -72,6 +72,11 @@ def test_tuning_roundtrip_and_limits():
     assert pb.get_tuning(5) == (6, 32)
     pb.set_tuning(5, *before)
     assert pb.get_tuning(5) == before
+    # a limb count maps to its kernel instance: 7 limbs run on the 8-limb one
+    before8 = pb.get_tuning(8)
+    pb.set_tuning(7, 3, 48)
+    assert pb.get_tuning(8) == (3, 48) and pb.get_tuning(7) == (3, 48)
+    pb.set_tuning(8, *before8)
     assert lib.pi_set_tuning(5, 0, 0) == -1          # run cap 0
     assert lib.pi_set_tuning(18, 0, 64) == -1        # no such limb count
     assert lib.pi_set_tuning(5, 65, 64) == -1
