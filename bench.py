@@ -86,7 +86,7 @@ def _pre_bits(run, Mmin, Mmax, a):
 
 # VALU instructions of the head kernel's data path per head term, from the
 # compiled gfx950 code (loop control and scheduling excluded):
-#  * binary64 classes (2^31 <= M < 2^48, windows of W = 3, 2, 1 bits): the
+#  * binary64 classes (2^29 <= M < 2^51, windows of W = 4, 3, 2, 1, 2 bits): the
 #    top 6 bits of X = E + 64L are the start value; each remaining bit costs
 #    a squaring (6 instructions, 9 with the second reduction from 2^48), each
 #    whole window 2 more (exponent digit, scale) and a short leading window 3
@@ -99,8 +99,8 @@ def _pre_bits(run, Mmin, Mmax, a):
 KERNEL_CLASSES = [
     ("22", 0, 1, 5, 73, -32),         # R = 2^32, lazy, start by doublings
     ("29", 2 ** 22, 1, 5, 67, -32),   # R = 2^32, lazy, run-quotient start
-    ("31", 2 ** 29, 1, 7, 67, -32),   # R = 2^32, reduced residues
-    ("f3", 2 ** 31, 3, 6, 87, 0),    # binary64, three-bit windows
+    ("f4", 2 ** 29, 4, 6, 88, 0),     # binary64, four-bit windows
+    ("f3", 2 ** 33, 3, 6, 87, 0),     # binary64, three-bit windows
     ("f2", 2 ** 42, 2, 6, 86, 0),    # binary64, two-bit windows
     ("f1", 2 ** 46, 1, 6, 86, 0),    # binary64, one-bit windows
     ("fr", 2 ** 48, 2, 9, 86, 0),    # binary64, two-bit windows, re-reduced

@@ -37,7 +37,6 @@ const int kHStep[2] = {4, 10};
 const int kHJ[2] = {4, 7};
 const int kLimbClasses[] = {1, 2, 3, 4, 5, 6, 8, 12, 17};
 
-constexpr uint64_t kClass32Limit = 1ull << 31;
 constexpr uint64_t kModulusLimit = 1ull << 54;
 
 int limb_class(uint32_t P) {
@@ -93,14 +92,14 @@ int make_plan(int formula, uint64_t n, uint32_t w, uint32_t P, uint32_t jmask, u
 }
 
 // Head segments of a plan, split by modulus range: below 2^22 (R = 2^32,
-// Montgomery one by doublings), [2^22, 2^29) (R = 2^32, lazy residues),
-// [2^29, 2^31) (R = 2^32), [2^31, 2^42), [2^42, 2^46) and [2^46, 2^48)
-// (binary64 with three-, two- and one-bit windows), [2^48, 2^51) (binary64,
-// two-bit windows, two reductions per squaring) and from 2^51 (R = 2^62).
+// Montgomery one by doublings), [2^22, 2^29) (R = 2^32, run-quotient start),
+// [2^29, 2^33), [2^33, 2^42), [2^42, 2^46) and [2^46, 2^48) (binary64 with
+// four-, three-, two- and one-bit windows), [2^48, 2^51) (binary64, two-bit
+// windows, two reductions per squaring) and from 2^51 (R = 2^62).
 void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &out) {
-  static const uint64_t kLim[7] = {1ull << 22, 1ull << 29, kClass32Limit, 1ull << 42,
-                                   1ull << 46, 1ull << 48,  1ull << 51};
-  static const uint32_t kCls[8] = {22, 29, 31, 42, 46, 48, 51, 64};
+  static const uint64_t kLim[7] = {1ull << 22, 1ull << 29, 1ull << 33, 1ull << 42,
+                                   1ull << 46, 1ull << 48, 1ull << 51};
+  static const uint32_t kCls[8] = {22, 29, 33, 42, 46, 48, 51, 64};
   for (int j = 0; j < kHJ[qp.formula]; ++j) {
     const HostSeries &s = kHSeries[qp.formula][j];
     const uint64_t kb = qp.hk0[j], ke = qp.hk1[j];
@@ -347,7 +346,7 @@ uint64_t number_chunks(std::vector<HeadSeg> &segs, uint32_t run_cap, uint64_t ch
     const uint64_t len = g.ke - g.kb;
     uint32_t run = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(run_cap, len / 1024u));
     g.pre = 0;
-    if (g.cls == 29 || g.cls == 31) {
+    if (g.cls == 29) {
       // the start value 2^32 - qM stays below 2M when 2^32 2a run < Mmin^2
       const uint64_t Mmin = s.a * g.kb + s.b;
       const uint64_t lim = (uint64_t)(((unsigned __int128)Mmin * Mmin >> 32) / (2u * s.a));

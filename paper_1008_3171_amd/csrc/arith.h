@@ -16,12 +16,12 @@
 //    term, left-aligned in L limbs, is t with its low 64L-P bits cleared.
 //
 // Modulus classes keep the instruction count down:
-//  * class 32 (M < 2^31): R = 2^32, residues kept below M;
-//  * binary64 (2^31 <= M < 2^51): plain (not Montgomery) residues held
+//  * class 32 (M < 2^29): R = 2^32, residues kept below 2M;
+//  * binary64 (2^29 <= M < 2^51): plain (not Montgomery) residues held
 //    exactly in doubles; a squaring is six full-rate fp64 instructions
 //    against sixteen integer ones for the same modulus in class 62 (nine
 //    from 2^48, with a second reduction), and exponent windows of up to
-//    three bits cost one more per window;
+//    four bits cost two more per window;
 //  * class 62 (2^51 <= M < 2^54): R = 2^62, residues in two 31-bit digits,
 //    kept below 8M;
 //  * R = 2^64 with residues below 2M (M < 2^60): the few tail terms.
@@ -33,7 +33,7 @@
 
 namespace pibbp {
 
-// ---- binary64 residues, 2^31 <= M < 2^51 -----------------------------------
+// ---- binary64 residues, 2^29 <= M < 2^51 -----------------------------------
 //
 // A residue is an integer-valued double x with |x| < M (signed, not reduced).
 // One step computes y = 2^d x^2 - qM:
@@ -43,13 +43,13 @@ namespace pibbp {
 //   2^53 in magnitude) and the last sum is exact for the same reason.
 // Bound: |H/M - q| <= 1/2 + (H/M)(2^-51 + 2^-53) and |Lo| <= 2^-53 H, so
 // |y| <= M/2 + 3 * 2^-52 * 2^d * M^2, which is below M while
-// 2^d M <= 2^52 / 6 (about 2^49.4). Three-bit windows (d <= 7) are therefore
-// exact for M < 2^42, two-bit windows (d <= 3) for M < 2^46 and one-bit
-// windows (d <= 1) for M < 2^48.
+// 2^d M <= 2^52 / 6 (about 2^49.4). Four-bit windows (d <= 15) are therefore
+// exact for M < 2^34, three-bit windows (d <= 7) for M < 2^42, two-bit
+// windows (d <= 3) for M < 2^46 and one-bit windows (d <= 1) for M < 2^48.
 
 // One Newton step toward 1/m from r: relative error e becomes e^2 + 2^-53.
 // From 1/(M - 2a), at most 2^-26.6 away for M >= 2^31 and a <= 10, one step
-// lands within 2^-52.2.
+// lands within 2^-52.2; from 2^29 (at most 2^-24.6 away) two steps do.
 __device__ __forceinline__ double recip_step(double m, double r) {
 #pragma clang fp contract(off)
   const double e = __builtin_fma(-m, r, 1.0);
@@ -88,7 +88,7 @@ __device__ __forceinline__ double rereduce_f64(double r, double M, double inv) {
   return __builtin_fma(-q, M, r);
 }
 
-// 2^v mod M, |result| < M, for v < 64 and M >= 2^31: the error term
+// 2^v mod M, |result| < M, for v < 64 and M >= 2^29: the error term
 // 2^v (2^-51 + 2^-53) is below 2^13, far under M/2.
 __device__ __forceinline__ double pow2_f64(uint32_t v, double M, double inv) {
 #pragma clang fp contract(off)
@@ -223,20 +223,9 @@ __device__ __forceinline__ uint32_t div_2_62(uint64_t M) {
   return q;
 }
 
-// ---- class 32: R = 2^32, residues in [0, M), M < 2^31 --------------------
+// ---- class 32: R = 2^32, residues in [0, 2M), M < 2^29 -------------------
 
-// x^2 2^b 2^-32 mod M for x < M: T = x (x << b) < 2M^2 and qM < 2^63, so
-// T + qM fits in 64 bits; its high half is below 2M; one conditional
-// subtraction brings it below M.
-__device__ __forceinline__ uint32_t sqr_redc32(uint32_t x, uint32_t b, uint32_t M, uint32_t mp) {
-  uint32_t y = x << b;
-  uint64_t T = (uint64_t)x * y;
-  uint32_t q = (uint32_t)T * mp;
-  uint32_t r = (uint32_t)((T + (uint64_t)q * M) >> 32);
-  return min(r, r - M);
-}
-
-// Lazy variant for M < 2^29: residues stay in [0, 2M). With x < 2M,
+// x^2 2^b 2^-32 mod M, lazily: residues stay in [0, 2M). With x < 2M,
 // y = x 2^b < 4M < 2^31, T = x y < 8M^2 and T + qM < 2^62, so the result is
 // below 8M^2/2^32 + M <= 2M and no subtraction is needed.
 __device__ __forceinline__ uint32_t sqr_redc32_lazy(uint32_t x, uint32_t b, uint32_t M,

@@ -202,17 +202,18 @@ __device__ __forceinline__ void lane_run62(uint64_t k0, uint32_t run, uint32_t p
   }
 }
 
-// Binary64 terms of one lane, 2^31 <= M < 2^51: s = 2^X mod M with
+// Binary64 terms of one lane, 2^29 <= M < 2^51: s = 2^X mod M with
 // X = E + 64L by a left-to-right ladder over W-bit windows (W squarings, the
-// window's value folded into the last one as a power of two); W = 3 for
-// M < 2^42, 2 for M < 2^46, 1 for M < 2^48, and from there W = 2 with a
-// second reduction after every squaring (kRe). The top t = min(6, bitlen X) bits v of X
+// window's value folded into the last one as a power of two); W = 4 for
+// M < 2^33, 3 for M < 2^42, 2 for M < 2^46, 1 for M < 2^48, and from there
+// W = 2 with a second reduction after every squaring (kRe). The top t = min(6, bitlen X) bits v of X
 // give the start 2^v mod M directly; the remaining bits begin with one short
 // window (their count mod W) and then whole windows at multiples of W. The
 // whole windows above bit S = 32 - (32 mod W) are read from X >> S and the
 // rest from the low word, so none straddles two words. The reciprocal of
-// each modulus comes from the previous one by a Newton step.
-template <int L, int W, bool kRe>
+// each modulus comes from the previous one by kNewton Newton steps (two
+// below 2^33, where the moduli are closest together relatively).
+template <int L, int W, bool kRe, int kNewton>
 __device__ __forceinline__ void lane_runf(uint64_t k0, uint32_t run, uint64_t kend, uint64_t a,
                                           uint64_t b, uint64_t dc, uint64_t step, uint32_t P,
                                           uint64_t (&sum)[L]) {
@@ -268,19 +269,19 @@ __device__ __forceinline__ void lane_runf(uint64_t k0, uint32_t run, uint64_t ke
     if (i < nv) add_limbs<L>(sum, t);
     Md += dMd;
     inv = recip_step(Md, inv);
+    if (kNewton > 1) inv = recip_step(Md, inv);
   }
 }
 
-// Class-32 terms of one lane (R = 2^32; X = E + 64L - 32). Three variants,
-// chosen per segment by the modulus range:
-//  * kLazy (M < 2^29): residues in [0, 2M), 4 instructions per step plus the
-//    exponent bit; otherwise (2^29 <= M < 2^31) residues in [0, M).
+// Class-32 terms of one lane (R = 2^32, M < 2^29; X = E + 64L - 32), with
+// residues in [0, 2M) (4 instructions per step plus the exponent bit). Two
+// variants, chosen per segment by the modulus range:
 //  * kRunStart (M >= 2^22): the Montgomery one is g = 2^32 - qM with
 //    q = floor(2^32 / M_last) for the lane's run; the host keeps runs short
 //    enough that g < 2M. Below 2^22 it comes from doublings of 2^bl - M.
 // The k = 0 term of a b = 1 series has M = 1 and value 2^E mod 1 = 0; it is
 // computed on garbage and not added.
-template <int L, bool kLazy, bool kRunStart>
+template <int L, bool kRunStart>
 __device__ __forceinline__ void lane_run32(uint64_t k0, uint32_t run, uint64_t kend, uint64_t a,
                                            uint64_t b, uint64_t dc, uint64_t step, uint32_t P,
                                            uint64_t (&sum)[L]) {
@@ -299,23 +300,12 @@ __device__ __forceinline__ void lane_run32(uint64_t k0, uint32_t run, uint64_t k
     const int nb = bitlen64(Xw);
     const uint32_t M32 = (uint32_t)M;
     const uint32_t mp = neg_inv32(M32);
-    uint32_t x;
-    if (kRunStart) {
-      x = 0u - q * M32;  // 2^32 - qM, below 2M
-      if (!kLazy) x = min(x, x - M32);
-    } else {
-      x = mont_one32(M32);
-    }
+    uint32_t x = kRunStart ? 0u - q * M32 : mont_one32(M32);  // below 2M
     const uint32_t xl = (uint32_t)X, xh = (uint32_t)(X >> 32);
-    if (kLazy) {
-      for (int j = nb - 33; j >= 0; --j) x = sqr_redc32_lazy(x, (xh >> j) & 1u, M32, mp);
-      for (int j = (nb < 32 ? nb : 32) - 1; j >= 0; --j)
-        x = sqr_redc32_lazy(x, (xl >> j) & 1u, M32, mp);
-      x = min(x, x - M32);
-    } else {
-      for (int j = nb - 33; j >= 0; --j) x = sqr_redc32(x, (xh >> j) & 1u, M32, mp);
-      for (int j = (nb < 32 ? nb : 32) - 1; j >= 0; --j) x = sqr_redc32(x, (xl >> j) & 1u, M32, mp);
-    }
+    for (int j = nb - 33; j >= 0; --j) x = sqr_redc32_lazy(x, (xh >> j) & 1u, M32, mp);
+    for (int j = (nb < 32 ? nb : 32) - 1; j >= 0; --j)
+      x = sqr_redc32_lazy(x, (xl >> j) & 1u, M32, mp);
+    x = min(x, x - M32);
     uint64_t t[L];
     hensel32<L>(x, M32, mp, t);
     apply_masks<L>(t, msk);
@@ -354,13 +344,13 @@ __device__ void head_chunks(const HeadSeg *segs, int nseg, uint64_t nchunks,
     for (int i = 0; i < L; ++i) sum[i] = 0;
     switch (sg.cls) {
       case 64: lane_run62<L>(k0, run, sg.pre, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
-      case 51: lane_runf<L, 2, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
-      case 48: lane_runf<L, 1, false>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
-      case 46: lane_runf<L, 2, false>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
-      case 42: lane_runf<L, 3, false>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
-      case 31: lane_run32<L, false, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
-      case 29: lane_run32<L, true, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
-      default: lane_run32<L, true, false>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+      case 51: lane_runf<L, 2, true, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+      case 48: lane_runf<L, 1, false, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+      case 46: lane_runf<L, 2, false, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+      case 42: lane_runf<L, 3, false, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+      case 33: lane_runf<L, 4, false, 2>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+      case 29: lane_run32<L, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+      default: lane_run32<L, false>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
     }
     if (neg) neg_limbs<L>(sum);
     wg_fold<L>(sum, red, sums, pend, &pend_off, sg.acc_off, acc, ctr, &next);

@@ -21,7 +21,7 @@ struct HeadSeg {
   uint32_t run;        // indices per lane per chunk; a chunk is 256 * run indices
   uint8_t formula, j;
   uint8_t cls;         // arithmetic by modulus: R = 2^32 Montgomery 22 (M < 2^22),
-                       // 29 (< 2^29), 31 (< 2^31); binary64 42 (< 2^42), 46 (< 2^46),
+                       // 29 (< 2^29); binary64 33 (< 2^33), 42 (< 2^42), 46 (< 2^46),
                        // 48 (< 2^48), 51 (< 2^51); 64: R = 2^62 Montgomery (M < 2^54)
   uint8_t pre;         // class 62: exponent bits taken into the ladder's start value
 };

@@ -8,9 +8,10 @@
  *
  * Reads lines "M d x re inv_mode" on stdin (inv_mode 0: inv = 1/M correctly
  * rounded; 1: one Newton step from 1/(M - 20), as after the previous modulus
- * of a lane with a = 10) and prints "y ok" per line, where ok is 1 when both
+ * of a lane with a = 10; 2: two such steps) and prints "y ok" per line, where ok is 1 when both
  * intermediate results were below 2^53 in magnitude (so exact) and |y| < M.
- * Also answers "L M X W re" lines with the full ladder's 2^X mod M.
+ * Also answers "L M X W re steps" lines with the full ladder's 2^X mod M
+ * (steps: Newton steps per modulus, as in inv_mode).
  */
 #include <math.h>
 #include <stdint.h>
@@ -24,7 +25,8 @@ static double newton(double m, double r) {
 
 static double inverse(double M, int mode) {
   if (mode == 0) return 1.0 / M;
-  return newton(M, 1.0 / (M - 20.0));
+  const double r = newton(M, 1.0 / (M - 20.0));
+  return mode == 1 ? r : newton(M, r);
 }
 
 static int step(double x, int d, double M, double inv, int re, double *out) {
@@ -42,8 +44,8 @@ static int step(double x, int d, double M, double inv, int re, double *out) {
 
 /* 2^X mod M by the kernel's ladder: start 2^v for the top 6 bits, one short
  * window, then W-bit windows; returns the residue in [0, M) or -1. */
-static long long ladder(unsigned long long M, unsigned long long X, int W, int re) {
-  const double Md = (double)M, inv = inverse(Md, 1);
+static long long ladder(unsigned long long M, unsigned long long X, int W, int re, int steps) {
+  const double Md = (double)M, inv = inverse(Md, steps);
   const int nb = X ? 64 - __builtin_clzll(X) : 0;
   const int rest = nb < 6 ? 0 : nb - 6;
   const int lead = rest % W, top = rest - lead;
@@ -79,9 +81,9 @@ int main(void) {
       printf("%.0f %d\n", y, ok);
     } else {
       unsigned long long M, X;
-      int W, re;
-      if (scanf("%llu %llu %d %d", &M, &X, &W, &re) != 4) return 1;
-      printf("%lld\n", ladder(M, X, W, re));
+      int W, re, steps;
+      if (scanf("%llu %llu %d %d %d", &M, &X, &W, &re, &steps) != 5) return 1;
+      printf("%lld\n", ladder(M, X, W, re, steps));
     }
   }
   return 0;

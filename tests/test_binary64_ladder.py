@@ -22,9 +22,11 @@ import pytest
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-# (window bits W, lowest modulus, first modulus past the class, second reduction)
-CLASSES = [(3, 2 ** 31, 2 ** 42, False), (2, 2 ** 42, 2 ** 46, False),
-           (1, 2 ** 46, 2 ** 48, False), (2, 2 ** 48, 2 ** 51, True)]
+# (window bits W, lowest modulus, first modulus past the class, second
+# reduction, Newton steps per modulus)
+CLASSES = [(4, 2 ** 29, 2 ** 33, False, 2), (3, 2 ** 33, 2 ** 42, False, 1),
+           (2, 2 ** 42, 2 ** 46, False, 1), (1, 2 ** 46, 2 ** 48, False, 1),
+           (2, 2 ** 48, 2 ** 51, True, 1)]
 
 
 @pytest.fixture(scope="module")
@@ -49,8 +51,8 @@ def edge_moduli(lo, hi, rng):
     return ms
 
 
-@pytest.mark.parametrize("W,lo,hi,re", CLASSES)
-def test_step_is_exact_at_the_edges(model, W, lo, hi, re):
+@pytest.mark.parametrize("W,lo,hi,re,steps", CLASSES)
+def test_step_is_exact_at_the_edges(model, W, lo, hi, re, steps):
     rng = random.Random(W * 100 + hi.bit_length())
     cases = []
     for M in edge_moduli(lo, hi, rng):
@@ -59,7 +61,7 @@ def test_step_is_exact_at_the_edges(model, W, lo, hi, re):
              [rng.randrange(-bound, bound + 1) for _ in range(12)]
         for x in xs:
             for d in {0, 1, (1 << W) - 1}:
-                for mode in (0, 1):
+                for mode in (0, steps):
                     cases.append((M, d, x, mode))
     out = model(["S %d %d %d %d %d" % (M, d, x, int(re), mode) for M, d, x, mode in cases])
     for (M, d, x, mode), line in zip(cases, out):
@@ -71,8 +73,8 @@ def test_step_is_exact_at_the_edges(model, W, lo, hi, re):
             assert abs(y) <= M // 2 + 1
 
 
-@pytest.mark.parametrize("W,lo,hi,re", CLASSES)
-def test_ladder_equals_pow(model, W, lo, hi, re):
+@pytest.mark.parametrize("W,lo,hi,re,steps", CLASSES)
+def test_ladder_equals_pow(model, W, lo, hi, re, steps):
     rng = random.Random(7 + W + hi.bit_length())
     cases = []
     for M in edge_moduli(lo, hi, rng):
@@ -80,7 +82,7 @@ def test_ladder_equals_pow(model, W, lo, hi, re):
             X = rng.getrandbits(rng.randrange(1, 62)) | 1
             cases.append((M, X))
         cases += [(M, 1), (M, 63), (M, 64), (M, 2 ** 61 - 1), (M, 2 ** 61 + 12345)]
-    out = model(["L %d %d %d %d" % (M, X, W, int(re)) for M, X in cases])
+    out = model(["L %d %d %d %d %d" % (M, X, W, int(re), steps) for M, X in cases])
     for (M, X), line in zip(cases, out):
         assert int(line) == pow(2, X, M), (M, X, W, re)
 
