@@ -85,35 +85,32 @@ def _pre_bits(run, Mmin, Mmax, a):
 
 
 # VALU instructions of the head kernel's data path per head term, from the
-# compiled gfx950 code (loop control and scheduling excluded):
-#  * binary64 classes (2^29 <= M < 2^51, windows of W = 4, 3, 2, 1, 2 bits): the
-#    top 6 bits of X = E + 64L are the start value; each remaining bit costs
-#    a squaring (6 instructions, 9 with the second reduction from 2^48), each
-#    whole window 2 more (exponent digit, scale) and a short leading window 3
-#    more; about 86 per term for the start,
-#    reciprocal, residue, 32-bit inverse, the ten-digit Hensel division at
-#    L = 5, the mask and the accumulation;
-#  * integer classes (Montgomery): a fixed cost per ladder bit of
-#    X = E + 64L + offset (class 62 folds `pre` top bits into its start).
-#   (name, first modulus, W, per bit, per term, X offset - 64L)
+# compiled gfx950 code (loop control and scheduling excluded). A term's ladder
+# runs over the bits of X = E + 64L + offset, minus the bits its start value
+# takes (binary64: the top 6; class 62: `pre`; class 32: none). Each of the
+# remaining r bits costs one squaring, each whole W-bit window 2 more
+# (exponent digit, scale) and a short leading window (r mod W bits) 3 more.
+# The per-term part covers the start value, the reciprocal or the 32-bit
+# inverse, the residue, the Hensel division at L = 5, the mask and the
+# accumulation.
+#   (name, first modulus, W, per squaring, per window, per term, offset)
 KERNEL_CLASSES = [
-    ("22", 0, 1, 5, 73, -32),         # R = 2^32, lazy, start by doublings
-    ("29", 2 ** 22, 1, 5, 67, -32),   # R = 2^32, lazy, run-quotient start
-    ("f4", 2 ** 29, 4, 6, 88, 0),     # binary64, four-bit windows
-    ("f3", 2 ** 33, 3, 6, 87, 0),     # binary64, three-bit windows
-    ("f2", 2 ** 42, 2, 6, 86, 0),    # binary64, two-bit windows
-    ("f1", 2 ** 46, 1, 6, 86, 0),    # binary64, one-bit windows
-    ("fr", 2 ** 48, 2, 9, 86, 0),    # binary64, two-bit windows, re-reduced
-    ("62", 2 ** 51, 1, 16, 104, -62), # R = 2^62, two 31-bit digits
+    ("22", 0, 3, 3, 2, 75, -32),        # R = 2^32 Montgomery, doubling start
+    ("27", 2 ** 22, 2, 3, 2, 67, -32),  # R = 2^32, run-quotient start
+    ("29", 2 ** 27, 1, 3, 2, 67, -32),  # R = 2^32, run-quotient start
+    ("f4", 2 ** 29, 4, 6, 2, 88, 0),    # binary64
+    ("f3", 2 ** 33, 3, 6, 2, 87, 0),
+    ("f2", 2 ** 42, 2, 6, 2, 86, 0),
+    ("f1", 2 ** 46, 1, 6, 2, 86, 0),
+    ("fr", 2 ** 48, 2, 9, 2, 86, 0),    # binary64 with a second reduction
+    ("62", 2 ** 51, 1, 16, 0, 104, -62),  # R = 2^62, two 31-bit digits
 ]
 
 
-def _term_ops(cls, W, per_bit, fixed, nb, pre):
-    if cls[0] == "f":
-        rest = max(0, nb - 6)
-        return fixed + per_bit * rest + 2 * (rest // W) + (3 if rest % W else 0)
-    start = min(pre, nb) if cls == "62" else 0
-    return fixed + per_bit * (nb - start)
+def _term_ops(cls, W, per_sq, per_win, fixed, nb, pre):
+    start = 6 if cls[0] == "f" else (pre if cls == "62" else 0)
+    r = max(0, nb - start)
+    return fixed + per_sq * r + per_win * (r // W) + (3 if r % W else 0)
 
 
 def valu_ops_per_launch(formula, n, P, run=64):
@@ -133,8 +130,8 @@ def valu_ops_per_launch(formula, n, P, run=64):
         def first_k(mlim):
             return min(K, max(0, -(-(mlim - b) // a)))
 
-        bounds = [first_k(m) for _, m, _, _, _, _ in KERNEL_CLASSES] + [K]
-        for i, (cls, _, W, per_bit, fixed, off) in enumerate(KERNEL_CLASSES):
+        bounds = [first_k(m) for _, m, _, _, _, _, _ in KERNEL_CLASSES] + [K]
+        for i, (cls, _, W, per_sq, per_win, fixed, off) in enumerate(KERNEL_CLASSES):
             lo, hi = bounds[i], bounds[i + 1]
             if lo >= hi:
                 continue
@@ -150,7 +147,7 @@ def valu_ops_per_launch(formula, n, P, run=64):
                 lowX = 1 << (bl - 1) if bl > 0 else 0
                 kmax = min(hi - 1, (base - lowX) // step) if bl > 0 else hi - 1
                 cnt = kmax - k + 1
-                total += cnt * _term_ops(cls, W, per_bit, fixed, bl, pre)
+                total += cnt * _term_ops(cls, W, per_sq, per_win, fixed, bl, pre)
                 terms += cnt
                 k = kmax + 1
     return total, terms

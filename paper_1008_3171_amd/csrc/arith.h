@@ -225,6 +225,24 @@ __device__ __forceinline__ uint32_t div_2_62(uint64_t M) {
 
 // ---- class 32: R = 2^32, residues in [0, 2M), M < 2^29 -------------------
 
+// x^2 2^-32 mod M, lazily (x < 2M, M < 2^30): T = x^2 < 4M^2, so
+// (T + qM) / 2^32 < 4M^2 / 2^32 + M < 2M. Three instructions.
+__device__ __forceinline__ uint32_t sqr_redc32_plain(uint32_t x, uint32_t M, uint32_t mp) {
+  const uint64_t T = (uint64_t)x * x;
+  const uint32_t q = (uint32_t)T * mp;
+  return (uint32_t)((T + (uint64_t)q * M) >> 32);
+}
+
+// With a window digit d: x^2 2^d 2^-32 mod M stays below 2M while
+// 2^(d+2) M < 2^32, i.e. d <= 3 for M < 2^27 and d <= 7 for M < 2^23, and
+// x 2^d < 2^31 then fits a word.
+__device__ __forceinline__ uint32_t sqr_redc32_digit(uint32_t x, uint32_t d, uint32_t M,
+                                                     uint32_t mp) {
+  const uint64_t T = (uint64_t)x * (x << d);
+  const uint32_t q = (uint32_t)T * mp;
+  return (uint32_t)((T + (uint64_t)q * M) >> 32);
+}
+
 // x^2 2^b 2^-32 mod M, lazily: residues stay in [0, 2M). With x < 2M,
 // y = x 2^b < 4M < 2^31, T = x y < 8M^2 and T + qM < 2^62, so the result is
 // below 8M^2/2^32 + M <= 2M and no subtraction is needed.

@@ -274,17 +274,22 @@ __device__ __forceinline__ void lane_runf(uint64_t k0, uint32_t run, uint64_t ke
 }
 
 // Class-32 terms of one lane (R = 2^32, M < 2^29; X = E + 64L - 32), with
-// residues in [0, 2M) (4 instructions per step plus the exponent bit). Two
-// variants, chosen per segment by the modulus range:
+// residues in [0, 2M): a Montgomery squaring is 3 instructions, and W-bit
+// exponent windows (W = 3 below 2^23, 2 below 2^27, else 1) apply each
+// window's digit as 2^d in its last squaring (2 more). The bits of X start
+// with one short window (bitlen mod W bits); whole windows above bit
+// S = 32 - (32 mod W) are read from X >> S. Two start values:
 //  * kRunStart (M >= 2^22): the Montgomery one is g = 2^32 - qM with
 //    q = floor(2^32 / M_last) for the lane's run; the host keeps runs short
 //    enough that g < 2M. Below 2^22 it comes from doublings of 2^bl - M.
 // The k = 0 term of a b = 1 series has M = 1 and value 2^E mod 1 = 0; it is
 // computed on garbage and not added.
-template <int L, bool kRunStart>
+template <int L, int W, bool kRunStart>
 __device__ __forceinline__ void lane_run32(uint64_t k0, uint32_t run, uint64_t kend, uint64_t a,
                                            uint64_t b, uint64_t dc, uint64_t step, uint32_t P,
                                            uint64_t (&sum)[L]) {
+  constexpr int S = 32 - 32 % W;
+  constexpr uint32_t kDigit = (1u << W) - 1u;
   const uint64_t dM = 2u * a, ndX = 0u - 2u * uniform64(step);
   uint64_t M = a * k0 + b;
   uint64_t X = dc + 64ull * L - 32ull - step * k0;
@@ -298,13 +303,25 @@ __device__ __forceinline__ void lane_run32(uint64_t k0, uint32_t run, uint64_t k
   uint64_t Xw = uniform64(X);
   for (uint32_t i = 0; i < nw; ++i, M += dM, X += ndX, Xw += ndX) {
     const int nb = bitlen64(Xw);
+    const int lead = nb % W, top = nb - lead;
     const uint32_t M32 = (uint32_t)M;
     const uint32_t mp = neg_inv32(M32);
     uint32_t x = kRunStart ? 0u - q * M32 : mont_one32(M32);  // below 2M
-    const uint32_t xl = (uint32_t)X, xh = (uint32_t)(X >> 32);
-    for (int j = nb - 33; j >= 0; --j) x = sqr_redc32_lazy(x, (xh >> j) & 1u, M32, mp);
-    for (int j = (nb < 32 ? nb : 32) - 1; j >= 0; --j)
-      x = sqr_redc32_lazy(x, (xl >> j) & 1u, M32, mp);
+    if (lead) {
+      for (int j = 1; j < lead; ++j) x = sqr_redc32_plain(x, M32, mp);
+      x = sqr_redc32_digit(x, (uint32_t)(X >> top) & ((1u << lead) - 1u), M32, mp);
+    }
+    const uint32_t xhi = (uint32_t)(X >> S), xlo = (uint32_t)X;
+    for (int p = top - W; p >= S; p -= W) {
+#pragma unroll
+      for (int j = 1; j < W; ++j) x = sqr_redc32_plain(x, M32, mp);
+      x = sqr_redc32_digit(x, (xhi >> (p - S)) & kDigit, M32, mp);
+    }
+    for (int p = (top < S ? top : S) - W; p >= 0; p -= W) {
+#pragma unroll
+      for (int j = 1; j < W; ++j) x = sqr_redc32_plain(x, M32, mp);
+      x = sqr_redc32_digit(x, (xlo >> p) & kDigit, M32, mp);
+    }
     x = min(x, x - M32);
     uint64_t t[L];
     hensel32<L>(x, M32, mp, t);
@@ -349,8 +366,9 @@ __device__ void head_chunks(const HeadSeg *segs, int nseg, uint64_t nchunks,
       case 46: lane_runf<L, 2, false, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
       case 42: lane_runf<L, 3, false, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
       case 33: lane_runf<L, 4, false, 2>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
-      case 29: lane_run32<L, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
-      default: lane_run32<L, false>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+      case 29: lane_run32<L, 1, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+      case 27: lane_run32<L, 2, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+      default: lane_run32<L, 3, false>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
     }
     if (neg) neg_limbs<L>(sum);
     wg_fold<L>(sum, red, sums, pend, &pend_off, sg.acc_off, acc, ctr, &next);
