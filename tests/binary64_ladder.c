@@ -8,8 +8,9 @@
  *
  * Reads lines "M d x re inv_mode" on stdin (inv_mode 0: inv = 1/M correctly
  * rounded; 1: one Newton step from 1/(M - 20), as after the previous modulus
- * of a lane with a = 10; 2: two such steps) and prints "y ok" per line, where ok is 1 when both
- * intermediate results were below 2^53 in magnitude (so exact) and |y| < M.
+ * of a lane with a = 10; 2: two such steps) and prints "y ok" per line,
+ * where ok is 1 when both intermediate results were below 2^53 in magnitude
+ * (so exact) and |y| < M.
  * Also answers "L M X W re steps" lines with the full ladder's 2^X mod M
  * (steps: Newton steps per modulus, as in inv_mode).
  */
@@ -62,7 +63,8 @@ static long long ladder(unsigned long long M, unsigned long long X, int W, int r
       if (!step(x, 0, Md, inv, re, &x)) return -1;
     if (!step(x, (int)((X >> q) & ((1u << W) - 1u)), Md, inv, re, &x)) return -1;
   }
-  if (x < 0) x += Md;
+  x = fma(-floor(x * inv), Md, x);  /* [0, M): x * inv stays inside (-1, 1) */
+  if (x < 0 || x >= Md) return -1;
   double y = x + 0x1p52;
   unsigned long long u;
   memcpy(&u, &y, 8);
