@@ -86,6 +86,23 @@ def test_slices_across_every_modulus_class_boundary(cut):
                     oracle.sum_slice(f, j, n - 1, k0, k1, P, 8)[0], (f, j, n, k0, k1, P)
 
 
+def test_slices_at_the_largest_moduli():
+    # the last indices whose modulus is below the 2^54 limit (class 62's top),
+    # with exponents near 2^61; one index further is refused
+    rng = random.Random(54)
+    for f in FORMULAS:
+        rows, step, _ = oracle.series_table(f)
+        for j, (s, c, a, b) in enumerate(rows):
+            k1 = (2 ** 54 - 1 - b) // a + 1          # a (k1 - 1) + b < 2^54
+            n = 2 ** 61 + rng.randrange(10 ** 6)
+            for k0 in (k1 - 1, k1 - rng.randrange(2, 3000)):
+                P = rng.choice([64, 320, 1088])
+                assert gpu_slice(f, j, n, k0, k1, P) == \
+                    oracle.sum_slice(f, j, n - 1, k0, k1, P, 8)[0], (f, j, k0, k1, P)
+            with pytest.raises(pb.PiError):
+                gpu_slice(f, j, n, k1, k1 + 1, 64)
+
+
 def test_slices_large_moduli():
     # moduli near 2^40 (n = 10^12) and near 2^50 (n = 2*10^15), ragged lengths
     rng = random.Random(17)
