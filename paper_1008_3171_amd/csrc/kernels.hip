@@ -398,7 +398,8 @@ __global__ void zero_kernel(unsigned long long *p, uint64_t n) {
 
 // ---- tail terms and finalize ------------------------------------------------
 
-// Tail term (E < 0) at L limbs: floor(2^(64L+E) / M), low bits above P cleared.
+// Tail term (E < 0) at L limbs: floor(2^(64L+E) / M) with its low 64L - P bits
+// cleared.
 // For M > 1 it is floor(2^(64L)/M) shifted right by -E (the same floor), and
 // floor(2^(64L)/M) is the head formula with E = 0 (r = 1).
 template <int L>
