@@ -101,8 +101,7 @@ KERNEL_CLASSES = [
     ("f4", 2 ** 29, 4, 6, 2, 88, 0),    # binary64
     ("f3", 2 ** 33, 3, 6, 2, 87, 0),
     ("f2", 2 ** 42, 2, 6, 2, 86, 0),
-    ("f1", 2 ** 46, 1, 6, 2, 86, 0),
-    ("fr", 2 ** 48, 2, 9, 2, 86, 0),    # binary64 with a second reduction
+    ("fr", 2 ** 48, 2, 6, 5, 86, 0),    # binary64, second reduction per window
     ("62", 2 ** 51, 1, 16, 0, 104, -62),  # R = 2^62, two 31-bit digits
 ]
 

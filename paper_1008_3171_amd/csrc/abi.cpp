@@ -94,13 +94,13 @@ int make_plan(int formula, uint64_t n, uint32_t w, uint32_t P, uint32_t jmask, u
 // Head segments of a plan, split by modulus range: below 2^22 (R = 2^32,
 // Montgomery one by doublings, three-bit windows), [2^22, 2^27) and
 // [2^27, 2^29) (R = 2^32, run-quotient start, two- and one-bit windows),
-// [2^29, 2^33), [2^33, 2^42), [2^42, 2^46) and [2^46, 2^48) (binary64 with
-// four-, three-, two- and one-bit windows), [2^48, 2^51) (binary64, two-bit
-// windows, two reductions per squaring) and from 2^51 (R = 2^62).
+// [2^29, 2^33), [2^33, 2^42) and [2^42, 2^48) (binary64 with four-, three-
+// and two-bit windows), [2^48, 2^51) (binary64, two-bit windows, a second
+// reduction per window) and from 2^51 (R = 2^62).
 void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &out) {
-  static const uint64_t kLim[8] = {1ull << 22, 1ull << 27, 1ull << 29, 1ull << 33,
-                                   1ull << 42, 1ull << 46, 1ull << 48, 1ull << 51};
-  static const uint32_t kCls[9] = {22, 27, 29, 33, 42, 46, 48, 51, 64};
+  static const uint64_t kLim[7] = {1ull << 22, 1ull << 27, 1ull << 29, 1ull << 33,
+                                   1ull << 42, 1ull << 48, 1ull << 51};
+  static const uint32_t kCls[8] = {22, 27, 29, 33, 42, 48, 51, 64};
   for (int j = 0; j < kHJ[qp.formula]; ++j) {
     const HostSeries &s = kHSeries[qp.formula][j];
     const uint64_t kb = qp.hk0[j], ke = qp.hk1[j];
@@ -109,7 +109,7 @@ void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &
       const uint64_t k = Mlim > s.b ? (Mlim - s.b + s.a - 1) / s.a : 0;
       return std::min(std::max(k, kb), ke);
     };
-    const uint64_t cuts[10] = {kb,
+    const uint64_t cuts[9] = {kb,
                               first_k(kLim[0]),
                               first_k(kLim[1]),
                               first_k(kLim[2]),
@@ -117,7 +117,6 @@ void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &
                               first_k(kLim[4]),
                               first_k(kLim[5]),
                               first_k(kLim[6]),
-                              first_k(kLim[7]),
                               ke};
     HeadSeg g;
     memset(&g, 0, sizeof g);
@@ -126,7 +125,7 @@ void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &
     g.j = (uint32_t)j;
     g.P = qp.P;
     g.acc_off = acc_off;
-    for (int c = 0; c < 9; ++c) {
+    for (int c = 0; c < 8; ++c) {
       if (cuts[c] >= cuts[c + 1]) continue;
       g.kb = cuts[c];
       g.ke = cuts[c + 1];

@@ -19,9 +19,9 @@
 //  * class 32 (M < 2^29): R = 2^32, residues kept below 2M;
 //  * binary64 (2^29 <= M < 2^51): plain (not Montgomery) residues held
 //    exactly in doubles; a squaring is six full-rate fp64 instructions
-//    against sixteen integer ones for the same modulus in class 62 (nine
-//    from 2^48, with a second reduction), and exponent windows of up to
-//    four bits cost two more per window;
+//    against sixteen integer ones for the same modulus in class 62, exponent
+//    windows of up to four bits cost two more per window, and from 2^48 a
+//    second reduction per window three more;
 //  * class 62 (2^51 <= M < 2^54): R = 2^62, residues in two 31-bit digits,
 //    kept below 8M;
 //  * R = 2^64 with residues below 2M (M < 2^60): the few tail terms.
@@ -44,8 +44,17 @@ namespace pibbp {
 // Bound: |H/M - q| <= 1/2 + (H/M)(2^-51 + 2^-53) and |Lo| <= 2^-53 H, so
 // |y| <= M/2 + 3 * 2^-52 * 2^d * M^2, which is below M while
 // 2^d M <= 2^52 / 6 (about 2^49.4). Four-bit windows (d <= 15) are therefore
-// exact for M < 2^34, three-bit windows (d <= 7) for M < 2^42, two-bit
-// windows (d <= 3) for M < 2^46 and one-bit windows (d <= 1) for M < 2^48.
+// exact for M < 2^34 and three-bit windows (d <= 7) for M < 2^42.
+//
+// From 2^42 the reciprocal is tighter: one Newton step from the previous
+// modulus's reciprocal (at most 2^-37.7 away) leaves e^2 + 2^-53 with e^2 below
+// 2^-75, so |y| <= M/2 + kappa H with kappa = 3 * 2^-53 (inv, the rounding of
+// H inv, and Lo each 2^-53). Two-bit windows then keep |x| <= 0.75 M below
+// 2^48: from 0.75 M the first squaring gives at most 0.553 M and the second
+// (d <= 3) at most 0.73 M. From 2^48 to 2^51 a second reduction follows each
+// window: from |x| <= M/2 + 2 the first squaring gives at most 0.69 M, the
+// second at most 3.35 M (below 2^53, so still exact), and the reduction
+// returns |x| <= M/2 + 2.
 
 // One Newton step toward 1/m from r: relative error e becomes e^2 + 2^-53.
 // From 1/(M - 2a), at most 2^-26.6 away for M >= 2^31 and a <= 10, one step
@@ -56,8 +65,10 @@ __device__ __forceinline__ double recip_step(double m, double r) {
   return __builtin_fma(r, e, r);
 }
 
+// 1/m to within 2^-53 (1 + 2^-20) from the hardware reciprocal: three steps
+// leave any seed error below 2^-13 far below the final rounding.
 __device__ __forceinline__ double recip_f64(double m) {
-  return recip_step(m, recip_step(m, __builtin_amdgcn_rcp(m)));
+  return recip_step(m, recip_step(m, recip_step(m, __builtin_amdgcn_rcp(m))));
 }
 
 // y = 2^d x^2 mod M, |y| < M (bounds above).
@@ -78,10 +89,8 @@ __device__ __forceinline__ double sqr_f64(double x, double M, double inv) {
   return __builtin_fma(-q, M, h) + lo;
 }
 
-// For 2^48 <= M < 2^51 each squaring is followed by r - rint(r * inv) M,
-// three more instructions that bring any |r| < 2^53 back to |r| <= M/2 + 1.
-// From |x| <= 0.51 M and d <= 3, H <= 2.08 M^2, so the first stage's
-// remainder is at most M/2 + 2^-51 H < 2.6 M < 2^53 and stays exact.
+// The second reduction r - rint(r * inv) M: three instructions that bring
+// any |r| < 2^53 back to |r| <= M/2 + 2.
 __device__ __forceinline__ double rereduce_f64(double r, double M, double inv) {
 #pragma clang fp contract(off)
   const double q = __builtin_rint(r * inv);

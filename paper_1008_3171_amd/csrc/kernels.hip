@@ -205,8 +205,8 @@ __device__ __forceinline__ void lane_run62(uint64_t k0, uint32_t run, uint32_t p
 // Binary64 terms of one lane, 2^29 <= M < 2^51: s = 2^X mod M with
 // X = E + 64L by a left-to-right ladder over W-bit windows (W squarings, the
 // window's value folded into the last one as a power of two); W = 4 for
-// M < 2^33, 3 for M < 2^42, 2 for M < 2^46, 1 for M < 2^48, and from there
-// W = 2 with a second reduction after every squaring (kRe). The top t = min(6, bitlen X) bits v of X
+// M < 2^33, 3 for M < 2^42, 2 for M < 2^48, and from there W = 2 with a
+// second reduction after each window (kRe). The top t = min(6, bitlen X) bits v of X
 // give the start 2^v mod M directly; the remaining bits begin with one short
 // window (their count mod W) and then whole windows at multiples of W. The
 // whole windows above bit S = 32 - (32 mod W) are read from X >> S and the
@@ -239,11 +239,8 @@ __device__ __forceinline__ void lane_runf(uint64_t k0, uint32_t run, uint64_t ke
     const int rest = max(nb - 6, 0);
     const int lead = rest % W, top = rest - lead;
     double x = pow2_f64((uint32_t)(X >> rest), Md, inv);
-    auto sq = [&](double y) {
-      y = sqr_f64(y, Md, inv);
-      return kRe ? rereduce_f64(y, Md, inv) : y;
-    };
-    auto sqd = [&](double y, uint32_t dg) {
+    auto sq = [&](double y) { return sqr_f64(y, Md, inv); };
+    auto sqd = [&](double y, uint32_t dg) {  // a window's last squaring
       y = sqr_f64(y, (int)dg, Md, inv);
       return kRe ? rereduce_f64(y, Md, inv) : y;
     };
@@ -362,8 +359,7 @@ __device__ void head_chunks(const HeadSeg *segs, int nseg, uint64_t nchunks,
     switch (sg.cls) {
       case 64: lane_run62<L>(k0, run, sg.pre, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
       case 51: lane_runf<L, 2, true, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
-      case 48: lane_runf<L, 1, false, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
-      case 46: lane_runf<L, 2, false, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+      case 48: lane_runf<L, 2, false, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
       case 42: lane_runf<L, 3, false, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
       case 33: lane_runf<L, 4, false, 2>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
       case 29: lane_run32<L, 1, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;

@@ -8,7 +8,7 @@
 namespace pibbp {
 
 constexpr int PI_MAX_L = 17;          // ceil(PI_MAX_P / 64)
-constexpr int kMaxArgSegs = 63;       // 7 series x 9 modulus ranges
+constexpr int kMaxArgSegs = 56;       // 7 series x 8 modulus ranges
 
 // A range [kb, ke) of head indices (E >= 0) of series j of one query, all of
 // one modulus class; its chunks are numbered chunk0, chunk0 + 1, ...
@@ -21,7 +21,7 @@ struct HeadSeg {
   uint32_t run;        // indices per lane per chunk; a chunk is 256 * run indices
   uint8_t formula, j;
   uint8_t cls;         // arithmetic by modulus: R = 2^32 Montgomery 22 (M < 2^22),
-                       // 27 (< 2^27), 29 (< 2^29); binary64 33 (< 2^33), 42 (< 2^42), 46 (< 2^46),
+                       // 27 (< 2^27), 29 (< 2^29); binary64 33 (< 2^33), 42 (< 2^42),
                        // 48 (< 2^48), 51 (< 2^51); 64: R = 2^62 Montgomery (M < 2^54)
   uint8_t pre;         // class 62: exponent bits taken into the ladder's start value
 };

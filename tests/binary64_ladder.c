@@ -4,15 +4,17 @@
  * A residue is an integer-valued double |x| < M. One step forms
  * y = 2^d x^2 - qM as the kernel does: H = x * (2^d x) rounded,
  * Lo = fma(x, 2^d x, -H), q = rint(H * inv), y = fma(-q, M, H) + Lo, and for
- * moduli from 2^48 a second reduction y - rint(y * inv) M.
+ * moduli from 2^48 a second reduction y - rint(y * inv) M after each window.
  *
  * Reads lines "M d x re inv_mode" on stdin (inv_mode 0: inv = 1/M correctly
  * rounded; 1: one Newton step from 1/(M - 20), as after the previous modulus
  * of a lane with a = 10; 2: two such steps) and prints "y ok" per line,
  * where ok is 1 when both intermediate results were below 2^53 in magnitude
  * (so exact) and |y| < M.
- * Also answers "L M X W re steps" lines with the full ladder's 2^X mod M
- * (steps: Newton steps per modulus, as in inv_mode).
+ * "W M W d x re inv_mode" lines run one W-bit window with digit d from x and
+ * print "y ok" (ok: every intermediate below 2^53). "L M X W re steps" lines
+ * print the full ladder's 2^X mod M (steps: Newton steps per modulus, as in
+ * inv_mode).
  */
 #include <math.h>
 #include <stdint.h>
@@ -40,7 +42,15 @@ static int step(double x, int d, double M, double inv, int re, double *out) {
   int ok = fabs(r0) < 0x1p53 && fabs(y) < 0x1p53;
   if (re) y = fma(-rint(y * inv), M, y);
   *out = y;
-  return ok && fabs(y) < M;
+  return ok && (re || fabs(y) < M);
+}
+
+/* One W-bit window: W - 1 plain squarings and one with the digit d, then the
+ * second reduction when re; ok when every intermediate stayed exact. */
+static int window(double x, int W, int d, double M, double inv, int re, double *out) {
+  for (int j = 1; j < W; ++j)
+    if (!step(x, 0, M, inv, 0, &x)) return 0;
+  return step(x, d, M, inv, re, out);
 }
 
 /* 2^X mod M by the kernel's ladder: start 2^v for the top 6 bits, one short
@@ -53,16 +63,10 @@ static long long ladder(unsigned long long M, unsigned long long X, int W, int r
   const double p = ldexp(1.0, (int)(X >> rest));
   double x = fma(-rint(p * inv), Md, p);
   if (fabs(x) >= Md) return -1;
-  if (lead) {
-    for (int j = 1; j < lead; ++j)
-      if (!step(x, 0, Md, inv, re, &x)) return -1;
-    if (!step(x, (int)((X >> top) & ((1u << lead) - 1u)), Md, inv, re, &x)) return -1;
-  }
-  for (int q = top - W; q >= 0; q -= W) {
-    for (int j = 1; j < W; ++j)
-      if (!step(x, 0, Md, inv, re, &x)) return -1;
-    if (!step(x, (int)((X >> q) & ((1u << W) - 1u)), Md, inv, re, &x)) return -1;
-  }
+  if (lead && !window(x, lead, (int)((X >> top) & ((1u << lead) - 1u)), Md, inv, re, &x))
+    return -1;
+  for (int q = top - W; q >= 0; q -= W)
+    if (!window(x, W, (int)((X >> q) & ((1u << W) - 1u)), Md, inv, re, &x)) return -1;
   x = fma(-floor(x * inv), Md, x);  /* [0, M): x * inv stays inside (-1, 1) */
   if (x < 0 || x >= Md) return -1;
   double y = x + 0x1p52;
@@ -74,7 +78,14 @@ static long long ladder(unsigned long long M, unsigned long long X, int W, int r
 int main(void) {
   char kind[8];
   while (scanf("%7s", kind) == 1) {
-    if (kind[0] == 'S') {
+    if (kind[0] == 'W') {
+      double M, x;
+      int W, d, re, mode;
+      if (scanf("%lf %d %d %lf %d %d", &M, &W, &d, &x, &re, &mode) != 6) return 1;
+      double y;
+      const int ok = window(x, W, d, M, inverse(M, mode), re, &y);
+      printf("%.0f %d\n", y, ok);
+    } else if (kind[0] == 'S') {
       double M, x;
       int d, re, mode;
       if (scanf("%lf %d %lf %d %d", &M, &d, &x, &re, &mode) != 5) return 1;
