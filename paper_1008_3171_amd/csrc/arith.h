@@ -152,12 +152,6 @@ __device__ __forceinline__ uint64_t sqr_redc64(uint64_t x, uint32_t b, uint64_t 
   return hi + h + (lo != 0u ? 1u : 0u);
 }
 
-// Montgomery reduction of a single x < 2M: x 2^-64 mod M, in [0, M].
-__device__ __forceinline__ uint64_t redc64(uint64_t x, uint64_t M, uint64_t mp) {
-  uint64_t q = x * mp;
-  return __umul64hi(q, M) + (x != 0u ? 1u : 0u);
-}
-
 // 2^64 mod M (the Montgomery form of 1), M odd, 3 <= M < 2^60: start from
 // 2^bl - M == 2^bl (mod M), bl = bit length of M, then double 64 - bl times.
 __device__ __forceinline__ uint64_t mont_one64(uint64_t M) {
@@ -252,18 +246,7 @@ __device__ __forceinline__ uint32_t sqr_redc32_digit(uint32_t x, uint32_t d, uin
   return (uint32_t)((T + (uint64_t)q * M) >> 32);
 }
 
-// x^2 2^b 2^-32 mod M, lazily: residues stay in [0, 2M). With x < 2M,
-// y = x 2^b < 4M < 2^31, T = x y < 8M^2 and T + qM < 2^62, so the result is
-// below 8M^2/2^32 + M <= 2M and no subtraction is needed.
-__device__ __forceinline__ uint32_t sqr_redc32_lazy(uint32_t x, uint32_t b, uint32_t M,
-                                                    uint32_t mp) {
-  const uint32_t y = x << b;
-  const uint64_t T = (uint64_t)x * y;
-  const uint32_t q = (uint32_t)T * mp;
-  return (uint32_t)((T + (uint64_t)q * M) >> 32);
-}
-
-// floor(2^32 / M) for 2^22 <= M < 2^31 (restoring division; at most 11
+// floor(2^32 / M) for 2^22 <= M < 2^29 (restoring division; at most 11
 // quotient bits).
 __device__ __forceinline__ uint32_t div_2_32(uint32_t M) {
   uint64_t r = 1ull << 32;
