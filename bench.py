@@ -346,8 +346,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path has no multi-GPU code (a query's index "
-              "ranges would shard across GPUs with one 40-byte exchange at the end); "
-              "run with --gpus 1", file=sys.stderr)
+              "ranges would shard across GPUs with one exchange of its carry-save counters, "
+              "80 bytes at P = 320, at the end); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
