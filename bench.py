@@ -181,7 +181,7 @@ def cpu_baseline(formula, n, P, target_s=12.0):
 
 
 def batch_vs_loop(pb, torch, count=4096, seed=1008):
-    """Config 4: the seeded 4096-query batch as one pi_extract_batch call and as
+    """The seeded 4096-query batch as one pi_extract_batch call and as
     a loop of pi_extract_ex calls (one query per launch) on the same stream.
     Both are timed with HIP events on that stream; outputs must be identical."""
     from paper_1008_3171_amd import workloads
@@ -251,7 +251,7 @@ def batch_vs_loop(pb, torch, count=4096, seed=1008):
 
 
 def serving_bench(pb, torch, count=1000, seed=3171, hi_exp=10.0, rho=0.8):
-    """Config 5, scaled: `count` queries of the seeded serving stream
+    """The serving stream, scaled: `count` queries of the seeded serving stream
     (n = floor(10^U), U ~ U(3, hi_exp), BBP or Bellard 50/50, w in {64, 256},
     P = w + 64). First every query arrives at once, which measures capacity
     (queries/s); then the same queries arrive as a Poisson stream at rho times
@@ -299,14 +299,14 @@ def paper_slice(pb, torch):
             "terms_per_s": 7 * (k1 - k0) / s}
 
 
-def other_configs(pb, torch):
-    """Configs 1 and 2 as single queries: Bellard n = 10^6 (64 bits, P = 96),
+def other_workloads(pb, torch):
+    """Smaller single queries: Bellard n = 10^6 (64 bits, P = 96),
     Bellard and BBP at n = 10^10 (256 bits, P = 320)."""
     stream = torch.cuda.current_stream()
     rows = {}
-    for name, f, n, w, P in (("config1_bellard_n1e6", pb.BELLARD, 10 ** 6, 64, 96),
-                             ("config2_bellard_n1e10", pb.BELLARD, 10 ** 10, 256, 320),
-                             ("config2_bbp_n1e10", pb.BBP, 10 ** 10, 256, 320)):
+    for name, f, n, w, P in (("bellard_n1e6_P96", pb.BELLARD, 10 ** 6, 64, 96),
+                             ("bellard_n1e10_P320", pb.BELLARD, 10 ** 10, 256, 320),
+                             ("bbp_n1e10_P320", pb.BBP, 10 ** 10, 256, 320)):
         out = torch.zeros(pb.limbs(P), dtype=torch.int64, device="cuda")
         st = torch.zeros(4, dtype=torch.int32, device="cuda")
         pb.extract(f, n, w, P, out=out, status=st, stream=stream)
@@ -426,7 +426,7 @@ def main():
         res = subprocess.run([probe], capture_output=True, text=True, timeout=120, check=True)
         rec["valu_rates"] = [json.loads(l) for l in res.stdout.splitlines() if l.strip()]
     if not args.no_batch:
-        rec["other_configs"] = other_configs(pb, torch)
+        rec["other_workloads"] = other_workloads(pb, torch)
         rec["batch"] = batch_vs_loop(pb, torch)
         rec["paper_slice"] = paper_slice(pb, torch)
     if not args.no_serving:

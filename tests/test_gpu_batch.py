@@ -66,7 +66,7 @@ def test_workspace_and_null_status():
     assert [x[0] for x in a] == [x[0] for x in c]
 
 
-def test_batch_config4_equals_single_queries():
+def test_batch_of_4096_log_uniform_queries_equals_single_queries():
     # the benchmark's 4096-query batch (seed 1008): every result equals the
     # single-query call; a seeded sample of the small ones also the oracle's
     specs = workloads.batch_queries(4096, seed=1008)

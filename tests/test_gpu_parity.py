@@ -56,7 +56,7 @@ def test_small_positions_every_limb_class():
         assert got == want, (f, n, w, P)
 
 
-def test_config1_bellard_1e6():
+def test_bellard_n1e6_64_bits_P96():
     # 700,001 head terms, moduli < 2^20, 64 result bits + 32 guard bits
     got = gpu_extract(pb.BELLARD, 10 ** 6, 64, 96)
     want = oracle.extract(oracle.BELLARD, 10 ** 6, 64, 96, 8)
@@ -161,7 +161,7 @@ def test_table_2_2_rows(m):
     assert S >> 64 == hex_bits(row[3], 256)
 
 
-def test_config2_bbp_and_bellard_agree_at_1e10():
+def test_bbp_and_bellard_agree_at_n1e10():
     a = gpu_extract(pb.BELLARD, 10 ** 10, 256, 320)
     b = gpu_extract(pb.BBP, 10 ** 10, 256, 320)
     assert a[2] and b[2]
