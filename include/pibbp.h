@@ -26,8 +26,8 @@
  *    caller; the library never frees them. Query tables are HOST pointers.
  *  - Calls are asynchronous on `stream`: argument validation is synchronous
  *    and returns an error code; results are ready when the stream is.
- *  - Limits: 1 <= P <= PI_MAX_P; every modulus a_j*k+b_j below 2^54 and
- *    n + P below 2^62 (otherwise PI_EUNSUPPORTED).
+ *  - Limits: 1 <= P <= PI_MAX_P; the modulus a_j*k+b_j of every index a call
+ *    sums below 2^54, and n + P below 2^62 (otherwise PI_EUNSUPPORTED).
  *  - Calls on one device share internal scratch per stream; calls on
  *    different streams may overlap, calls on one stream are serialized.
  */
@@ -80,8 +80,7 @@ typedef struct {
 } pi_status;
 
 /* nbits bits of pi starting at 1-based position n, with P = nbits + 64 (the
- * 64 guard bits certify the result; section 3.1's "compute with more
- * precision than you report").
+ * 64 guard bits are what certification, section 3.1, examines).
  *   out: device uint64[ceil((nbits+64)/64)], the left-aligned P-bit sum S.
  * Returns PI_OK or an error; certification is reported by pi_extract_ex. */
 PI_API int pi_extract(int formula, uint64_t n, uint32_t nbits, uint64_t *out, hipStream_t stream);
