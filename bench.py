@@ -299,6 +299,29 @@ def paper_slice(pb, torch):
             "terms_per_s": 7 * (k1 - k0) / s}
 
 
+def integer_only(pb, torch, formula, n, w, P, fast_ms):
+    """The headline query again with pi_set_arith(PI_ARITH_INTEGER): integer
+    Montgomery arithmetic for every modulus, same bits."""
+    stream = torch.cuda.current_stream()
+    out = torch.zeros(pb.limbs(P), dtype=torch.int64, device="cuda")
+    st = torch.zeros(4, dtype=torch.int32, device="cuda")
+    pb.set_arith(pb.ARITH_INTEGER)
+    try:
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        pb.extract(formula, n, w, P, out=out, status=st, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+    finally:
+        pb.set_arith(pb.ARITH_FAST)
+    ms = e0.elapsed_time(e1)
+    terms = pb.head_terms(formula, n)
+    return {"ms": ms, "terms_per_s": terms / (ms * 1e-3), "fast_over_integer": ms / fast_ms,
+            "S": "%x" % pb.to_int(out, P), "certified": pb.status_of(st)[0] == pb.PI_OK}
+
+
 def other_workloads(pb, torch):
     """Smaller single queries: Bellard n = 10^6 (64 bits, P = 96),
     Bellard and BBP at n = 10^10 (256 bits, P = 320)."""
@@ -338,6 +361,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-integer", action="store_true",
+                    help="skip timing the query again in integer-only arithmetic")
     ap.add_argument("--measure-peak", action="store_true",
                     help="run the VALU issue-rate probe and report its rates")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -420,6 +445,10 @@ def main():
         h = re.search(r"^12 \d+ \d+ ([0-9A-F]+)$", row, re.M).group(1)
         ref = int(h, 16) >> (4 * len(h) - 255)
         rec["matches_table_2_2_m12"] = ((S >> (P - w)) & ((1 << 255) - 1)) == ref
+    if not args.no_integer:
+        io = integer_only(pb, torch, formula, n, w, P, ms)
+        io["same_bits"] = io.pop("S") == "%x" % S
+        rec["integer_only"] = io
     if args.measure_peak:
         import subprocess
         probe = os.path.join(ROOT, "paper_1008_3171_amd", "probe", "valu_rates")

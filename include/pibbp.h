@@ -174,6 +174,21 @@ PI_API uint64_t pi_head_terms(int formula, uint64_t n);
 PI_API int pi_set_tuning(int limbs, uint32_t wg_per_cu, uint32_t run_cap);
 PI_API int pi_get_tuning(int limbs, uint32_t *wg_per_cu, uint32_t *run_cap);
 
+/* Arithmetic of the head terms' modular exponentiation (section 4.2 names
+ * successive squaring and Montgomery's method). Both modes compute the same
+ * exact integers, so every result is bit-identical:
+ *   PI_ARITH_FAST (default): moduli from 2^29 to 2^51 run on integer-valued
+ *     binary64 numbers whose every operation is exact (fp64 FMA issues at the
+ *     same rate as a 32-bit integer multiply-add and needs fewer
+ *     instructions); Montgomery below and above;
+ *   PI_ARITH_INTEGER: integer Montgomery arithmetic for every modulus.
+ * The mode is read when a query is planned (pi_extract*, pi_sum_slice*,
+ * pi_extract_batch, pi_batch_create, pi_server_submit). PI_EINVAL for an
+ * unknown mode. */
+enum { PI_ARITH_FAST = 0, PI_ARITH_INTEGER = 1 };
+PI_API int pi_set_arith(int mode);
+PI_API int pi_get_arith(void);
+
 /* Static text for a return code. */
 PI_API const char *pi_strerror(int code);
 

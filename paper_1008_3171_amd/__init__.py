@@ -68,6 +68,10 @@ def load():
         lib.pi_set_tuning.restype = i32
         lib.pi_get_tuning.argtypes = [i32, ctypes.POINTER(u32), ctypes.POINTER(u32)]
         lib.pi_get_tuning.restype = i32
+        lib.pi_set_arith.argtypes = [i32]
+        lib.pi_set_arith.restype = i32
+        lib.pi_get_arith.argtypes = []
+        lib.pi_get_arith.restype = i32
         _lib = lib
         _apply_tuning_cache()
     return _lib
@@ -103,6 +107,22 @@ def get_tuning(limbs: int):
     if rc != 0:
         raise PiError(rc, "pi_get_tuning")
     return a.value, b.value
+
+
+ARITH_FAST = 0
+ARITH_INTEGER = 1
+
+
+def set_arith(mode: int):
+    """pi_set_arith: ARITH_FAST (exact binary64 where cheaper) or ARITH_INTEGER
+    (integer Montgomery arithmetic everywhere); results are bit-identical."""
+    rc = load().pi_set_arith(mode)
+    if rc != 0:
+        raise PiError(rc, "pi_set_arith")
+
+
+def get_arith() -> int:
+    return int(load().pi_get_arith())
 
 
 def _torch():

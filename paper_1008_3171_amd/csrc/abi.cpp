@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -91,16 +92,32 @@ int make_plan(int formula, uint64_t n, uint32_t w, uint32_t P, uint32_t jmask, u
   return PI_OK;
 }
 
-// Head segments of a plan, split by modulus range: below 2^22 (R = 2^32,
-// Montgomery one by doublings, three-bit windows), [2^22, 2^27) and
-// [2^27, 2^29) (R = 2^32, run-quotient start, two- and one-bit windows),
-// [2^29, 2^33), [2^33, 2^42) and [2^42, 2^48) (binary64 with four-, three-
-// and two-bit windows), [2^48, 2^51) (binary64, two-bit windows, a second
-// reduction per window) and from 2^51 (R = 2^62).
+// Arithmetic of the head terms (pi_set_arith): PI_ARITH_FAST uses exact
+// binary64 residues where they are cheapest, PI_ARITH_INTEGER integer
+// Montgomery arithmetic everywhere. Both give the same bits.
+std::atomic<int> g_arith{PI_ARITH_FAST};
+
+// Head segments of a plan, split by modulus range.
+//  * PI_ARITH_FAST: below 2^22 (R = 2^32, Montgomery one by doublings,
+//    three-bit windows), [2^22, 2^27) and [2^27, 2^29) (R = 2^32, run-quotient
+//    start, two- and one-bit windows), [2^29, 2^33), [2^33, 2^42) and
+//    [2^42, 2^48) (binary64 with four-, three- and two-bit windows),
+//    [2^48, 2^51) (binary64, two-bit windows, a second reduction per window)
+//    and from 2^51 (R = 2^62).
+//  * PI_ARITH_INTEGER: the same below 2^29, [2^29, 2^31) (R = 2^32, reduced
+//    residues), then R = 2^62 split at 2^36 so that the small moduli, where a
+//    lane run's start value has the most slack to cover, do not limit the
+//    run length and start bits of the rest.
 void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &out) {
-  static const uint64_t kLim[7] = {1ull << 22, 1ull << 27, 1ull << 29, 1ull << 33,
-                                   1ull << 42, 1ull << 48, 1ull << 51};
-  static const uint32_t kCls[8] = {22, 27, 29, 33, 42, 48, 51, 64};
+  static const uint64_t kFastLim[7] = {1ull << 22, 1ull << 27, 1ull << 29, 1ull << 33,
+                                       1ull << 42, 1ull << 48, 1ull << 51};
+  static const uint32_t kFastCls[8] = {22, 27, 29, 33, 42, 48, 51, 64};
+  static const uint64_t kIntLim[5] = {1ull << 22, 1ull << 27, 1ull << 29, 1ull << 31, 1ull << 36};
+  static const uint32_t kIntCls[6] = {22, 27, 29, 31, 64, 64};
+  const bool fast = g_arith.load() == PI_ARITH_FAST;
+  const uint64_t *lim = fast ? kFastLim : kIntLim;
+  const uint32_t *cls = fast ? kFastCls : kIntCls;
+  const int ncls = fast ? 8 : 6;
   for (int j = 0; j < kHJ[qp.formula]; ++j) {
     const HostSeries &s = kHSeries[qp.formula][j];
     const uint64_t kb = qp.hk0[j], ke = qp.hk1[j];
@@ -109,15 +126,10 @@ void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &
       const uint64_t k = Mlim > s.b ? (Mlim - s.b + s.a - 1) / s.a : 0;
       return std::min(std::max(k, kb), ke);
     };
-    const uint64_t cuts[9] = {kb,
-                              first_k(kLim[0]),
-                              first_k(kLim[1]),
-                              first_k(kLim[2]),
-                              first_k(kLim[3]),
-                              first_k(kLim[4]),
-                              first_k(kLim[5]),
-                              first_k(kLim[6]),
-                              ke};
+    uint64_t cuts[9];
+    cuts[0] = kb;
+    for (int c = 1; c < ncls; ++c) cuts[c] = first_k(lim[c - 1]);
+    cuts[ncls] = ke;
     HeadSeg g;
     memset(&g, 0, sizeof g);
     g.d = qp.d;
@@ -125,11 +137,11 @@ void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &
     g.j = (uint32_t)j;
     g.P = qp.P;
     g.acc_off = acc_off;
-    for (int c = 0; c < 8; ++c) {
+    for (int c = 0; c < ncls; ++c) {
       if (cuts[c] >= cuts[c + 1]) continue;
       g.kb = cuts[c];
       g.ke = cuts[c + 1];
-      g.cls = kCls[c];
+      g.cls = cls[c];
       out.push_back(g);
     }
   }
@@ -347,7 +359,7 @@ uint64_t number_chunks(std::vector<HeadSeg> &segs, uint32_t run_cap, uint64_t ch
     const uint64_t len = g.ke - g.kb;
     uint32_t run = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(run_cap, len / 1024u));
     g.pre = 0;
-    if (g.cls == 27 || g.cls == 29) {
+    if (g.cls == 27 || g.cls == 29 || g.cls == 31) {
       // the start value 2^32 - qM stays below 2M when 2^32 2a run < Mmin^2
       const uint64_t Mmin = s.a * g.kb + s.b;
       const uint64_t lim = (uint64_t)(((unsigned __int128)Mmin * Mmin >> 32) / (2u * s.a));
@@ -652,6 +664,14 @@ int pi_extract_batch(const pi_query *q, int count, uint64_t *out, pi_status *sta
   }
   return run_batch(bp, ws, out, status, stream);
 }
+
+int pi_set_arith(int mode) {
+  if (mode != PI_ARITH_FAST && mode != PI_ARITH_INTEGER) return PI_EINVAL;
+  g_arith.store(mode);
+  return PI_OK;
+}
+
+int pi_get_arith(void) { return g_arith.load(); }
 
 int pi_set_tuning(int limbs, uint32_t wg_per_cu, uint32_t run_cap) {
   if (limbs < 0 || limbs > PI_MAX_L || run_cap == 0 || run_cap > 4096 || wg_per_cu > 64)

@@ -270,10 +270,12 @@ __device__ __forceinline__ void lane_runf(uint64_t k0, uint32_t run, uint64_t ke
   }
 }
 
-// Class-32 terms of one lane (R = 2^32, M < 2^29; X = E + 64L - 32), with
-// residues in [0, 2M): a Montgomery squaring is 3 instructions, and W-bit
+// Class-32 terms of one lane (R = 2^32; X = E + 64L - 32). Below 2^29 the
+// residues stay in [0, 2M): a Montgomery squaring is 3 instructions, and W-bit
 // exponent windows (W = 3 below 2^23, 2 below 2^27, else 1) apply each
-// window's digit as 2^d in its last squaring (2 more). The bits of X start
+// window's digit as 2^d in its last squaring (2 more). With kReduced
+// (2^29 <= M < 2^31, one-bit windows) every squaring result is brought below
+// M (2 more): from x < M, x (x << b) < 2M^2 and the REDC result is below 2M. The bits of X start
 // with one short window (bitlen mod W bits); whole windows above bit
 // S = 32 - (32 mod W) are read from X >> S. Two start values:
 //  * kRunStart (M >= 2^22): the Montgomery one is g = 2^32 - qM with
@@ -281,7 +283,7 @@ __device__ __forceinline__ void lane_runf(uint64_t k0, uint32_t run, uint64_t ke
 //    enough that g < 2M. Below 2^22 it comes from doublings of 2^bl - M.
 // The k = 0 term of a b = 1 series has M = 1 and value 2^E mod 1 = 0; it is
 // computed on garbage and not added.
-template <int L, int W, bool kRunStart>
+template <int L, int W, bool kRunStart, bool kReduced = false>
 __device__ __forceinline__ void lane_run32(uint64_t k0, uint32_t run, uint64_t kend, uint64_t a,
                                            uint64_t b, uint64_t dc, uint64_t step, uint32_t P,
                                            uint64_t (&sum)[L]) {
@@ -304,6 +306,7 @@ __device__ __forceinline__ void lane_run32(uint64_t k0, uint32_t run, uint64_t k
     const uint32_t M32 = (uint32_t)M;
     const uint32_t mp = neg_inv32(M32);
     uint32_t x = kRunStart ? 0u - q * M32 : mont_one32(M32);  // below 2M
+    if (kReduced) x = min(x, x - M32);
     if (lead) {
       for (int j = 1; j < lead; ++j) x = sqr_redc32_plain(x, M32, mp);
       x = sqr_redc32_digit(x, (uint32_t)(X >> top) & ((1u << lead) - 1u), M32, mp);
@@ -313,11 +316,13 @@ __device__ __forceinline__ void lane_run32(uint64_t k0, uint32_t run, uint64_t k
 #pragma unroll
       for (int j = 1; j < W; ++j) x = sqr_redc32_plain(x, M32, mp);
       x = sqr_redc32_digit(x, (xhi >> (p - S)) & kDigit, M32, mp);
+      if (kReduced) x = min(x, x - M32);
     }
     for (int p = (top < S ? top : S) - W; p >= 0; p -= W) {
 #pragma unroll
       for (int j = 1; j < W; ++j) x = sqr_redc32_plain(x, M32, mp);
       x = sqr_redc32_digit(x, (xlo >> p) & kDigit, M32, mp);
+      if (kReduced) x = min(x, x - M32);
     }
     x = min(x, x - M32);
     uint64_t t[L];
@@ -362,6 +367,7 @@ __device__ void head_chunks(const HeadSeg *segs, int nseg, uint64_t nchunks,
       case 48: lane_runf<L, 2, false, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
       case 42: lane_runf<L, 3, false, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
       case 33: lane_runf<L, 4, false, 2>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+      case 31: lane_run32<L, 1, true, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
       case 29: lane_run32<L, 1, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
       case 27: lane_run32<L, 2, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
       default: lane_run32<L, 3, false>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;

@@ -65,6 +65,17 @@ def test_invalid_arguments_are_rejected_synchronously():
     assert lib.pi_extract_ex(1, 2 ** 55, 8, 72, dummy, null, null) == -4
 
 
+def test_arith_mode_roundtrip_and_limits():
+    lib = pb.load()
+    assert pb.get_arith() == pb.ARITH_FAST
+    pb.set_arith(pb.ARITH_INTEGER)
+    assert pb.get_arith() == pb.ARITH_INTEGER
+    pb.set_arith(pb.ARITH_FAST)
+    assert pb.get_arith() == pb.ARITH_FAST
+    assert lib.pi_set_arith(2) == -1 and lib.pi_set_arith(-1) == -1
+    assert pb.get_arith() == pb.ARITH_FAST
+
+
 def test_tuning_roundtrip_and_limits():
     lib = pb.load()
     before = pb.get_tuning(5)
