@@ -49,6 +49,14 @@ def load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libpibbp.so is not built; run python -m paper_1008_3171_amd.build")
+        # torch ships its own HIP runtime under the same soname. Loaded first,
+        # it is the one the library binds to, so the process keeps a single
+        # runtime that owns torch's memory and streams; loaded second, it
+        # would come in as a second runtime beside the system one.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(LIB_PATH)
         vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
         lib.pi_extract.argtypes = [i32, u64, u32, vp, vp]

@@ -107,10 +107,14 @@ int pi_server_create(uint32_t max_active, uint64_t step_terms, hipStream_t strea
                      pi_server **out) {
   if (!out || max_active == 0 || step_terms == 0) return PI_EINVAL;
   *out = nullptr;
+  // make the caller's device current first: hipMemGetInfo needs its context,
+  // and this may be the process's first GPU call
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipSetDevice(dev) != hipSuccess) return PI_EDEVICE;
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return PI_EDEVICE;
   // device bytes one slot can need: counters, result row and status, and its
-  // share of the step tables (up to 35 segments and one finalize record)
+  // share of the step tables (up to kMaxArgSegs segments and one finalize record)
   const size_t per_slot = kSlotCounters * 8u + PI_MAX_L * 8u + sizeof(pi_status) +
                           kMaxArgSegs * sizeof(HeadSeg) + sizeof(FinQuery);
   const uint64_t by_mem = (uint64_t)(free_b / 4u / per_slot);

@@ -1,6 +1,7 @@
 """The continuous-batching server: every query's result is bit-identical to
 pi_extract_ex alone, whatever else is in flight; slots are admitted and
 reused; a large query keeps its partial sum on the device across steps."""
+import os
 import random
 
 import pytest
@@ -93,3 +94,23 @@ def test_paper_scale_slice_subslices_match_oracle():
         P = 320
         got = pb.to_int(pb.sum_slice(pb.term_id(pb.BELLARD, j), n, k0, k1, P), P)
         assert got == oracle.sum_slice(oracle.BELLARD, j, n - 1, k0, k1, P, 8)[0], (j, k0)
+
+
+def test_server_in_a_process_that_loads_the_library_before_torch():
+    # the library loaded first (a host-only call) and then a server as the
+    # process's first GPU work: one HIP runtime, server creation works
+    import subprocess
+    import sys
+    code = ("import paper_1008_3171_amd as pb\n"
+            "assert pb.head_terms(pb.BELLARD, 10 ** 6) == 700001\n"
+            "s = pb.Server(max_active=1024, step_terms=1 << 20)\n"
+            "assert s.submit(pb.BELLARD, 9, 8, 72, 7)\n"
+            "while s.active():\n"
+            "    s.step()\n"
+            "(tag, S, code, N), = s.poll()\n"
+            "s.close()\n"
+            "assert tag == 7 and code == pb.PI_OK and S >> 64 == 0x3F\n"
+            "print('ok')\n")
+    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120,
+                         cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert res.returncode == 0 and "ok" in res.stdout, res.stderr[-2000:]
