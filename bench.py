@@ -86,30 +86,37 @@ def _pre_bits(run, Mmin, Mmax, a):
 
 # VALU instructions of the head kernel's data path per head term, from the
 # compiled gfx950 code (loop control and scheduling excluded). A term's ladder
-# runs over the bits of X = E + 64L + offset, minus the bits its start value
-# takes (binary64: the top 6; class 62: `pre`; class 32: none). Each of the
-# remaining r bits costs one squaring, each whole W-bit window 2 more
-# (exponent digit, scale) and a short leading window (r mod W bits) 3 more.
-# The per-term part covers the start value, the reciprocal or the 32-bit
-# inverse, the residue, the Hensel division at L = 5, the mask and the
-# accumulation.
+# runs over the bits of its exponent X, minus the bits its start value takes
+# (binary64: the top 6; class 62: `pre`; class 32: none). X is E for the
+# binary64 classes and E + 64L + offset for the integer ones, whose Hensel
+# division needs 2^(64L) r. Each of the remaining r bits costs one squaring,
+# each whole W-bit window 2 more (exponent digit, scale) and a short leading
+# window (r mod W bits) 3 more. The per-term part covers the start value, the
+# reciprocal or the 32-bit inverse and the division at L = 5 (binary64: long
+# division; integer: Hensel, mask and accumulation).
 #   (name, first modulus, W, per squaring, per window, per term, offset)
+# (binary64 per term at L = 5: seven 46-bit digits of 5 instructions each.)
 KERNEL_CLASSES = [
     ("22", 0, 3, 3, 2, 75, -32),        # R = 2^32 Montgomery, doubling start
     ("27", 2 ** 22, 2, 3, 2, 67, -32),  # R = 2^32, run-quotient start
     ("29", 2 ** 27, 1, 3, 2, 67, -32),  # R = 2^32, run-quotient start
-    ("f4", 2 ** 29, 4, 6, 2, 88, 0),    # binary64
-    ("f3", 2 ** 33, 3, 6, 2, 87, 0),
-    ("f2", 2 ** 42, 2, 6, 2, 86, 0),
-    ("fr", 2 ** 48, 2, 6, 5, 86, 0),    # binary64, second reduction per window
+    ("f4", 2 ** 29, 4, 6, 2, 49, 0),    # binary64
+    ("f3", 2 ** 33, 3, 6, 2, 48, 0),
+    ("f2", 2 ** 42, 2, 6, 2, 47, 0),
+    ("fr", 2 ** 48, 2, 6, 5, 47, 0),    # binary64, second reduction per window
     ("62", 2 ** 51, 1, 16, 0, 104, -62),  # R = 2^62, two 31-bit digits
 ]
+# The binary64 classes also take a carry step over each lane's digit sums
+# every 120 terms (28 instructions at L = 5) and add the sums to the lane's
+# limbs once per run of 256 (81).
+FP_EXTRA_PER_TERM = 28 / 120 + 81 / 256
 
 
 def _term_ops(cls, W, per_sq, per_win, fixed, nb, pre):
     start = 6 if cls[0] == "f" else (pre if cls == "62" else 0)
     r = max(0, nb - start)
-    return fixed + per_sq * r + per_win * (r // W) + (3 if r % W else 0)
+    flush = FP_EXTRA_PER_TERM if cls[0] == "f" else 0.0
+    return fixed + flush + per_sq * r + per_win * (r // W) + (3 if r % W else 0)
 
 
 def valu_ops_per_launch(formula, n, P, run=64):
@@ -138,7 +145,7 @@ def valu_ops_per_launch(formula, n, P, run=64):
             if cls == "62":
                 pre = _pre_bits(min(run, max(1, (hi - lo) // 1024)), a * lo + b,
                                 a * (hi - 1) + b, a)
-            base = d + c + 64 * L + off
+            base = d + c + (0 if cls[0] == "f" else 64 * L + off)
             k = lo
             while k < hi:
                 X = base - step * k
@@ -149,7 +156,7 @@ def valu_ops_per_launch(formula, n, P, run=64):
                 total += cnt * _term_ops(cls, W, per_sq, per_win, fixed, bl, pre)
                 terms += cnt
                 k = kmax + 1
-    return total, terms
+    return int(round(total)), terms
 
 
 def cpu_baseline(formula, n, P, target_s=12.0):

@@ -8,12 +8,17 @@
 //    one Montgomery reduction of x^2 * 2^b, so the doubling for a 1 bit costs
 //    a shift, not a multiplication. The ladder's target exponent is chosen so
 //    that the Montgomery form of its result is already s = 2^(E+64L) mod M.
-//  * division: with s = r*2^(64L) mod M, the quotient t = floor(r*2^(64L)/M)
-//    satisfies t*M = r*2^(64L) - s, so t = -s * M^-1 mod 2^(64L). That is an
-//    exact (Hensel) division, limb by limb from the bottom, using the same
-//    -M^-1 mod 2^64 the Montgomery reduction needs.
-//  * truncation to P bits: floor(t / 2^(64L-P)) = floor(r*2^P/M), so the P-bit
-//    term, left-aligned in L limbs, is t with its low 64L-P bits cleared.
+//  * division, integer classes: with s = r*2^(64L) mod M, the quotient
+//    t = floor(r*2^(64L)/M) satisfies t*M = r*2^(64L) - s, so
+//    t = -s * M^-1 mod 2^(64L). That is an exact (Hensel) division, limb by
+//    limb from the bottom, using the same -M^-1 mod 2^64 the Montgomery
+//    reduction needs. Truncation to P bits: floor(t / 2^(64L-P)) =
+//    floor(r*2^P/M), so the P-bit term, left-aligned in L limbs, is t with its
+//    low 64L-P bits cleared.
+//  * division, binary64 class: schoolbook long division of r 2^P by M from
+//    the top, in signed digits of about 40 bits, each one exact fp64 FMA
+//    rounding and one exact fp64 FMA remainder; a lane sums its terms' digits
+//    per position in doubles and turns the sums into limbs once per run.
 //
 // Modulus classes keep the instruction count down:
 //  * class 32 (M < 2^29): R = 2^32, residues kept below 2M;
@@ -394,6 +399,126 @@ __device__ __forceinline__ void clip_low(uint64_t (&t)[L], uint32_t P) {
   low_masks<L>(P, m);
 #pragma unroll
   for (int i = 0; i < L; ++i) t[i] &= m[i];
+}
+
+// ---- binary64 long division of one term --------------------------------------
+//
+// The P-bit term floor(r 2^P / M) of a residue r (integer-valued double,
+// |r| < M) in signed digits, most significant first: digit d (d = 0 the
+// lowest) holds bits [dB, dB + B) of the term; the top one, d = ne - 1 with
+// ne = ceil(P / B), holds the remaining bt = P - (ne - 1)B bits. From a
+// remainder y, a digit of b bits is q = rint(y 2^b / M) and the next remainder
+// y 2^b - qM:
+//   ys = y 2^b (exact); fma(ys, inv, C) with C = 1.5 * 2^52 rounds the exact
+//   product ys * inv to an integer in one step (spacing 1 in [2^52, 2^53),
+//   and |ys inv| <= 2^46 (1 + 2^-50) < 2^51), so q = that - C;
+//   y' = fma(-q, M, ys) is exact: its value is an integer below M.
+// With inv within 2^-52 of 1/M relatively, |ys inv - ys/M| <= 2^b 2^-52 <= 2^-6
+// (b <= 46), so |y'| <= M (1/2 + 2^-6) and every digit after the top one has
+// |q| <= 2^(B-1) + 2^(B-6) + 1; the top one |q| <= 2^bt + 1.
+// After the last digit r 2^P = M * sum_d q_d 2^(dB) + y_N with |y_N| < M, so
+// floor(r 2^P / M) = sum_d q_d 2^(dB) - [y_N < 0]. A negative r gives the term
+// of r + M, floor((r + M) 2^P / M) = floor(r 2^P / M) + 2^P, up to that 2^P,
+// which the sum mod 2^P drops.
+//
+// A lane sums its terms' digits per position in doubles. Every kFpCarryTerms
+// terms the sums are carried upward until each lies in [0, 2^B) (the carry
+// out of the top position lands at or above bit N B >= P and is dropped);
+// from there 120 more digits of |q| <= 2^46 + 1 keep every sum below
+// 121 * 2^46 + 120 < 2^53, so exact. At the end of the run the sums go into
+// the lane's limbs. B <= 46 bits per digit, as few digits per limb count L as
+// cover 64L bits: N B >= 64L >= P.
+constexpr uint32_t kFpCarryTerms = 120;
+constexpr int fp_digits(int L) { return (64 * L + 45) / 46; }
+constexpr int fp_digit_bits(int L) { return (64 * L + fp_digits(L) - 1) / fp_digits(L); }
+
+// Digits of one term from y = r into the per-position sums A; nneg counts the
+// terms whose last remainder is negative. bits[d] is B below the top digit,
+// bt for it and 0 above it (wave-uniform): a 0-bit digit is rint(y / M),
+// whose weight 2^P vanishes mod 2^P, as does A_d 2^(dB) for those d.
+template <int N>
+__device__ __forceinline__ void fp_term_digits(double y, double M, double inv,
+                                               const int (&bits)[N], double (&A)[N],
+                                               uint32_t &nneg) {
+#pragma clang fp contract(off)
+  constexpr double C = 0x1.8p52;
+#pragma unroll
+  for (int d = N - 1; d >= 0; --d) {
+    const double ys = __builtin_amdgcn_ldexp(y, bits[d]);
+    const double q = __builtin_fma(ys, inv, C) - C;
+    y = __builtin_fma(-q, M, ys);
+    A[d] += q;
+  }
+  nneg += y < 0.0 ? 1u : 0u;
+}
+
+// The digit sizes for P bits: ne = ceil(P / B) digits, the top one
+// P - (ne - 1)B bits, and 0 bits for positions from ne up.
+template <int N, int B>
+__device__ __forceinline__ void fp_digit_sizes(uint32_t P, int (&bits)[N]) {
+  const int ne = (int)((P + B - 1u) / B), bt = (int)P - (ne - 1) * B;
+#pragma unroll
+  for (int d = 0; d < N; ++d)
+    bits[d] = __builtin_amdgcn_readfirstlane(d < ne - 1 ? B : d == ne - 1 ? bt : 0);
+}
+
+// The carry step: subtracts nneg from the lowest position, then brings every
+// A_d into [0, 2^B) by moving floor(A_d / 2^B) up one position (each carry
+// is at most 122 in magnitude, so A_{d+1} plus it stays below 2^53); the
+// carry out of the top position is dropped.
+template <int N, int B>
+__device__ __forceinline__ void fp_carry_digits(double (&A)[N], uint32_t &nneg) {
+#pragma clang fp contract(off)
+  constexpr double kTwoB = (double)(1ull << B);
+  A[0] -= (double)nneg;
+  nneg = 0;
+#pragma unroll
+  for (int d = 0; d < N; ++d) {
+    const double c = __builtin_floor(__builtin_amdgcn_ldexp(A[d], -B));
+    A[d] = __builtin_fma(-c, kTwoB, A[d]);
+    if (d + 1 < N) A[d + 1] += c;
+  }
+}
+
+// Adds sum_d A_d 2^(dB) - nneg, mod 2^P, at bit 64L - P of the L-limb sum,
+// and clears A and nneg. After the carry step the digits occupy disjoint bit
+// fields and are packed with shifts known at compile time; the packed value
+// moves up by 64L - P bits (fewer than 64 masked_limbs(L), as a query uses
+// the smallest limb class that holds P), and bits from 64L up fall away.
+template <int L>
+__device__ __forceinline__ void fp_digits_to_limbs(double (&A)[fp_digits(L)], uint32_t &nneg,
+                                                   uint32_t P, uint64_t (&sum)[L]) {
+#pragma clang fp contract(off)
+  constexpr int N = fp_digits(L), B = fp_digit_bits(L);
+  fp_carry_digits<N, B>(A, nneg);
+  uint64_t V[L + 1];
+#pragma unroll
+  for (int i = 0; i <= L; ++i) V[i] = 0;
+#pragma unroll
+  for (int d = 0; d < N; ++d) {
+    const uint64_t u = (uint64_t)__double_as_longlong(A[d] + 0x1p52) & ((1ull << 52) - 1u);
+    const int pos = d * B, li = pos >> 6, off = pos & 63;
+    V[li] |= u << off;
+    if (off + B > 64) V[li + 1] |= u >> (64 - off);
+  }
+  const uint32_t z = 64u * L - P, zl = z >> 6, zb = z & 63u;
+  uint64_t Wl[L];
+#pragma unroll
+  for (int j = 0; j < L; ++j) Wl[j] = V[j];
+#pragma unroll
+  for (int c = 1; c < masked_limbs(L); ++c)
+    if (zl == (uint32_t)c) {
+#pragma unroll
+      for (int j = L - 1; j >= 0; --j) Wl[j] = j >= c ? V[j - c] : 0ull;
+    }
+  uint64_t T[L];
+#pragma unroll
+  for (int j = 0; j < L; ++j)
+    T[j] = zb ? (Wl[j] << zb) | (j ? Wl[j - 1] >> (64u - zb) : 0ull) : Wl[j];
+  add_limbs<L>(sum, T);
+#pragma unroll
+  for (int d = 0; d < N; ++d) A[d] = 0.0;
+  nneg = 0;
 }
 
 }  // namespace pibbp

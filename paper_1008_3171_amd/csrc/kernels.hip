@@ -202,8 +202,8 @@ __device__ __forceinline__ void lane_run62(uint64_t k0, uint32_t run, uint32_t p
   }
 }
 
-// Binary64 terms of one lane, 2^29 <= M < 2^51: s = 2^X mod M with
-// X = E + 64L by a left-to-right ladder over W-bit windows (W squarings, the
+// Binary64 terms of one lane, 2^29 <= M < 2^51: r = 2^E mod M by a
+// left-to-right ladder over W-bit windows (W squarings, the
 // window's value folded into the last one as a power of two); W = 4 for
 // M < 2^33, 3 for M < 2^42, 2 for M < 2^48, and from there W = 2 with a
 // second reduction after each window (kRe). The top t = min(6, bitlen X) bits v of X
@@ -212,21 +212,28 @@ __device__ __forceinline__ void lane_run62(uint64_t k0, uint32_t run, uint32_t p
 // whole windows above bit S = 32 - (32 mod W) are read from X >> S and the
 // rest from the low word, so none straddles two words. The reciprocal of
 // each modulus comes from the previous one by kNewton Newton steps (two
-// below 2^33, where the moduli are closest together relatively).
+// below 2^33, where the moduli are closest together relatively). The term
+// floor(r 2^P / M) is then divided out in binary64 digits (fp_term_digits),
+// summed per digit position (with a carry step every kFpCarryTerms terms) and
+// added to sum at the end of the run.
 template <int L, int W, bool kRe, int kNewton>
 __device__ __forceinline__ void lane_runf(uint64_t k0, uint32_t run, uint64_t kend, uint64_t a,
                                           uint64_t b, uint64_t dc, uint64_t step, uint32_t P,
                                           uint64_t (&sum)[L]) {
   constexpr int S = 32 - 32 % W;
   constexpr uint32_t kDigit = (1u << W) - 1u;
+  constexpr int N = fp_digits(L), B = fp_digit_bits(L);
   const uint64_t dM = 2u * a, ndX = 0u - 2u * uniform64(step);
-  uint64_t M = a * k0 + b;
-  uint64_t X = dc + 64ull * L - step * k0;
-  double Md = (double)M;
+  uint64_t X = dc - step * k0;
+  double Md = (double)(a * k0 + b);
   const double dMd = (double)dM;
   double inv = recip_f64(Md);
-  uint64_t msk[L];
-  low_masks<L>(P, msk);
+  int bits[N];
+  fp_digit_sizes<N, B>(P, bits);
+  double A[N];
+#pragma unroll
+  for (int d = 0; d < N; ++d) A[d] = 0.0;
+  uint32_t nneg = 0;
   // terms of this lane inside the chunk (nv) and of lane 0 (nw: lane 0 has
   // the wave's smallest k, so the wave stops after nw terms); lane 0's
   // exponent, the wave's largest, is kept in scalar registers
@@ -234,40 +241,42 @@ __device__ __forceinline__ void lane_runf(uint64_t k0, uint32_t run, uint64_t ke
   const uint32_t nv = k0 < ke ? (uint32_t)((ke - k0 + 1u) >> 1) : 0u;
   const uint32_t nw = kw < ke ? min(run, (uint32_t)((ke - kw + 1u) >> 1)) : 0u;
   uint64_t Xw = uniform64(X);
-  for (uint32_t i = 0; i < nw; ++i, M += dM, X += ndX, Xw += ndX) {
-    const int nb = bitlen64(Xw);
-    const int rest = max(nb - 6, 0);
-    const int lead = rest % W, top = rest - lead;
-    double x = pow2_f64((uint32_t)(X >> rest), Md, inv);
-    auto sq = [&](double y) { return sqr_f64(y, Md, inv); };
-    auto sqd = [&](double y, uint32_t dg) {  // a window's last squaring
-      y = sqr_f64(y, (int)dg, Md, inv);
-      return kRe ? rereduce_f64(y, Md, inv) : y;
-    };
-    if (lead) {
-      for (int j = 1; j < lead; ++j) x = sq(x);
-      x = sqd(x, (uint32_t)(X >> top) & ((1u << lead) - 1u));
-    }
-    const uint32_t xhi = (uint32_t)(X >> S), xlo = (uint32_t)X;
-    for (int p = top - W; p >= S; p -= W) {
+  for (uint32_t i0 = 0; i0 < nw; i0 += kFpCarryTerms) {
+    const uint32_t i1 = min(nw, i0 + kFpCarryTerms);
+    for (uint32_t i = i0; i < i1; ++i, X += ndX, Xw += ndX) {
+      const int nb = bitlen64(Xw);
+      const int rest = max(nb - 6, 0);
+      const int lead = rest % W, top = rest - lead;
+      double x = pow2_f64((uint32_t)(X >> rest), Md, inv);
+      auto sq = [&](double y) { return sqr_f64(y, Md, inv); };
+      auto sqd = [&](double y, uint32_t dg) {  // a window's last squaring
+        y = sqr_f64(y, (int)dg, Md, inv);
+        return kRe ? rereduce_f64(y, Md, inv) : y;
+      };
+      if (lead) {
+        for (int j = 1; j < lead; ++j) x = sq(x);
+        x = sqd(x, (uint32_t)(X >> top) & ((1u << lead) - 1u));
+      }
+      const uint32_t xhi = (uint32_t)(X >> S), xlo = (uint32_t)X;
+      for (int p = top - W; p >= S; p -= W) {
 #pragma unroll
-      for (int j = 1; j < W; ++j) x = sq(x);
-      x = sqd(x, (xhi >> (p - S)) & kDigit);
-    }
-    for (int p = (top < S ? top : S) - W; p >= 0; p -= W) {
+        for (int j = 1; j < W; ++j) x = sq(x);
+        x = sqd(x, (xhi >> (p - S)) & kDigit);
+      }
+      for (int p = (top < S ? top : S) - W; p >= 0; p -= W) {
 #pragma unroll
-      for (int j = 1; j < W; ++j) x = sq(x);
-      x = sqd(x, (xlo >> p) & kDigit);
+        for (int j = 1; j < W; ++j) x = sq(x);
+        x = sqd(x, (xlo >> p) & kDigit);
+      }
+      // x == 2^E (mod M), |x| < M; lanes past the chunk's end sit this out
+      if (i < nv) fp_term_digits<N>(x, Md, inv, bits, A, nneg);
+      Md += dMd;
+      inv = recip_step(Md, inv);
+      if (kNewton > 1) inv = recip_step(Md, inv);
     }
-    const uint64_t sres = residue_u64(x, Md, inv);  // == 2^(E + 64L) (mod M), in [0, M)
-    uint64_t t[L];
-    hensel_d32<L>(sres, M, neg_inv32((uint32_t)M), t);
-    apply_masks<L>(t, msk);
-    if (i < nv) add_limbs<L>(sum, t);
-    Md += dMd;
-    inv = recip_step(Md, inv);
-    if (kNewton > 1) inv = recip_step(Md, inv);
+    fp_carry_digits<N, B>(A, nneg);
   }
+  fp_digits_to_limbs<L>(A, nneg, P, sum);
 }
 
 // Class-32 terms of one lane (R = 2^32; X = E + 64L - 32). Below 2^29 the

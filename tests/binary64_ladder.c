@@ -15,6 +15,13 @@
  * print "y ok" (ok: every intermediate below 2^53). "L M X W re steps" lines
  * print the full ladder's 2^X mod M (steps: Newton steps per modulus, as in
  * inv_mode).
+ * "D M x P B N inv_mode" lines divide x 2^P by M in N signed digits, most
+ * significant first: ne = ceil(P / B) digits of B bits, the top one holding
+ * P - (ne - 1)B, and 0-bit digits above it. Each digit is
+ * q = fma(y 2^b, inv, 1.5 * 2^52) - 1.5 * 2^52, y <- fma(-q, M, y 2^b). Prints
+ * the N digits from the top, then 1 if the last remainder is negative, then
+ * ok (every remainder below M in magnitude and every rounded product below
+ * 2^51, so every step exact).
  */
 #include <math.h>
 #include <stdint.h>
@@ -78,7 +85,25 @@ static long long ladder(unsigned long long M, unsigned long long X, int W, int r
 int main(void) {
   char kind[8];
   while (scanf("%7s", kind) == 1) {
-    if (kind[0] == 'W') {
+    if (kind[0] == 'D') {
+      double M, x;
+      int P, B, N, mode;
+      if (scanf("%lf %lf %d %d %d %d", &M, &x, &P, &B, &N, &mode) != 6) return 1;
+      const double inv = inverse(M, mode), C = 0x1.8p52;
+      const int ne = (P + B - 1) / B, bt = P - (ne - 1) * B;
+      double y = x;
+      int ok = fabs(x) < M;
+      for (int d = N - 1; d >= 0; --d) {
+        const int b = d < ne - 1 ? B : d == ne - 1 ? bt : 0;
+        const double ys = ldexp(y, b);
+        ok = ok && fabs(ys * inv) < 0x1p51;
+        const double q = fma(ys, inv, C) - C;
+        y = fma(-q, M, ys);
+        ok = ok && fabs(y) < M;
+        printf("%.0f ", q);
+      }
+      printf("%d %d\n", y < 0.0, ok);
+    } else if (kind[0] == 'W') {
       double M, x;
       int W, d, re, mode;
       if (scanf("%lf %d %d %lf %d %d", &M, &W, &d, &x, &re, &mode) != 6) return 1;

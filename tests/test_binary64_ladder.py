@@ -11,7 +11,10 @@ land:
 `binary64_ladder.c` models the kernel's step with the C library's correctly
 rounded fma. Every window must give x^(2^W) 2^d mod M exactly, with every
 intermediate value below 2^53 and the result inside the invariant. The
-32-bit-digit Hensel division is checked by its recurrence in Python integers.
+binary64 long division that turns a residue into its P-bit term must give
+floor((x mod M) 2^P / M) mod 2^P from its signed digits, inside the digit
+bounds that keep a run's per-position sums exact. The 32-bit-digit Hensel
+division (integer classes) is checked by its recurrence in Python integers.
 """
 import os
 import random
@@ -112,3 +115,78 @@ def test_hensel_digit_recurrence():
             assert h < M
             t |= u << (32 * i)
         assert t == (-s * pow(M, -1, 2 ** (64 * L))) % 2 ** (64 * L)
+
+
+# limb counts the kernels are built for; a query of P bits uses the smallest
+# that holds it
+LIMB_CLASSES = [1, 2, 3, 4, 5, 6, 8, 12, 17]
+
+
+CARRY_TERMS = 120    # terms whose digits a lane sums between carry steps
+
+
+def digit_layout(P):
+    # the kernel's digit plan: as few digits as cover 64L bits, at most 46 bits
+    L = next(c for c in LIMB_CLASSES if 64 * c >= P)
+    N = -(-64 * L // 46)
+    return N, -(-64 * L // N)
+
+
+@pytest.mark.parametrize("W,lo,hi,re,steps,c", CLASSES)
+def test_long_division_gives_the_truncated_term(model, W, lo, hi, re, steps, c):
+    # x 2^P / M in signed digits: sum q_d 2^(dB) - [last remainder < 0] is
+    # floor((x mod M) 2^P / M) mod 2^P for residues anywhere in the ladder's
+    # invariant (negative ones included) and every limb class, with digits
+    # small enough that CARRY_TERMS of them, added to a carried sum below
+    # 2^B, sum exactly in a double
+    rng = random.Random(400 + hi.bit_length())
+    Ps = [1, 31, 32, 33, 64, 65, 96, 128, 150, 192, 200, 256, 260, 300, 320, 321, 384,
+          400, 512, 600, 768, 800, 1000, 1088]
+    cases = []
+    for M in edge_moduli(lo, hi, rng)[:9]:
+        bound = min(int(c * M) + (2 if re else 0), M - 1)
+        for x in (bound, -bound, 0, 1, -1, M // 2, -(M // 2), rng.randrange(-bound, bound + 1)):
+            for P in Ps:
+                cases.append((M, x, P, steps))
+    lines = []
+    for M, x, P, mode in cases:
+        N, B = digit_layout(P)
+        lines.append("D %d %d %d %d %d %d" % (M, x, P, B, N, mode))
+    out = model(lines)
+    for (M, x, P, mode), line in zip(cases, out):
+        N, B = digit_layout(P)
+        f = line.split()
+        qs = [int(v) for v in f[:N]][::-1]          # q_0 (lowest) first
+        neg, ok = int(f[N]), int(f[N + 1])
+        assert ok == 1, (M, x, P)
+        value = sum(q << (d * B) for d, q in enumerate(qs)) - neg
+        assert value % 2 ** P == ((x % M) << P) // M % 2 ** P, (M, x, P)
+        ne = -(-P // B)
+        bt = P - (ne - 1) * B
+        assert abs(qs[ne - 1]) <= 2 ** bt + 1, (M, x, P)
+        assert all(abs(q) <= 2 ** (B - 1) + 2 ** (B - 6) + 1 for q in qs[:ne - 1]), (M, x, P)
+        assert all(abs(q) <= 1 for q in qs[ne:]), (M, x, P)
+        # a carried sum (below 2^B) plus CARRY_TERMS digits, minus the count of
+        # negative remainders, plus the carry from below (at most 122)
+        assert B <= 46 and N * B >= P
+        assert 2 ** B + CARRY_TERMS * (2 ** B + 1) + CARRY_TERMS + 122 < 2 ** 53
+
+
+def test_long_division_of_random_residues(model):
+    # random moduli across the binary64 range, random residues and P
+    rng = random.Random(1008)
+    cases = []
+    for _ in range(3000):
+        M = rng.randrange(2 ** 29, 2 ** 51) | 1
+        x = rng.randrange(-(M // 2), M // 2 + 1)
+        P = rng.randrange(1, 1089)
+        cases.append((M, x, P))
+    out = model(["D %d %d %d %d %d 0" % (M, x, P, digit_layout(P)[1], digit_layout(P)[0])
+                 for M, x, P in cases])
+    for (M, x, P), line in zip(cases, out):
+        N, B = digit_layout(P)
+        f = line.split()
+        qs = [int(v) for v in f[:N]][::-1]
+        assert int(f[N + 1]) == 1
+        value = sum(q << (d * B) for d, q in enumerate(qs)) - int(f[N])
+        assert value % 2 ** P == ((x % M) << P) // M % 2 ** P, (M, x, P)

@@ -86,6 +86,45 @@ def test_slices_across_every_modulus_class_boundary(cut):
                     oracle.sum_slice(f, j, n - 1, k0, k1, P, 8)[0], (f, j, n, k0, k1, P)
 
 
+def test_binary64_division_every_limb_class_and_ragged_widths():
+    # the binary64 classes (2^29 <= M < 2^51) divide each residue out in
+    # digits of up to 46 bits, the top digit taking what is left of P and the
+    # digits above it none: P at both ends of every limb class and in between
+    rng = random.Random(64)
+    Ps = [1, 31, 33, 64, 65, 100, 128, 150, 192, 200, 256, 260, 300, 320, 321, 384, 400,
+          511, 512, 600, 768, 800, 1000, 1088]
+    for i, P in enumerate(Ps):
+        f = FORMULAS[i % 2]
+        rows, step, _ = oracle.series_table(f)
+        j = rng.randrange(len(rows))
+        s, c, a, b = rows[j]
+        for e in (30, 37, 45, 50):
+            ks = (2 ** e - b) // a
+            n = step * ks + rng.randrange(10 ** 6, 10 ** 9)
+            k0 = ks + rng.randrange(0, 1000)
+            k1 = k0 + rng.randrange(1, 5000)
+            assert gpu_slice(f, j, n, k0, k1, P) == \
+                oracle.sum_slice(f, j, n - 1, k0, k1, P, 8)[0], (f, j, n, k0, k1, P)
+
+
+def test_long_runs_carry_the_digit_sums():
+    # a lane carries its per-position digit sums every 120 terms and adds
+    # them to its limbs at the end of its run: runs of 512 (one workgroup per
+    # CU, run cap 4096) take four carry steps each
+    saved = pb.get_tuning(1)
+    try:
+        pb.set_tuning(1, 1, 4096)
+        f = pb.BELLARD
+        rows, step, _ = oracle.series_table(f)
+        s, c, a, b = rows[3]
+        k0 = (2 ** 40 - b) // a + 12345
+        k1 = k0 + 512 * 256 * 256 * 4 + 777
+        n = step * k1 + 10 ** 7
+        assert gpu_slice(f, 3, n, k0, k1, 64) == oracle.sum_slice(f, 3, n - 1, k0, k1, 64, 8)[0]
+    finally:
+        pb.set_tuning(1, *saved)
+
+
 def test_slices_at_the_largest_moduli():
     # the last indices whose modulus is below the 2^54 limit (class 62's top),
     # with exponents near 2^61; one index further is refused
