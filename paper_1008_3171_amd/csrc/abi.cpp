@@ -273,7 +273,7 @@ struct Tuning {
   uint32_t run_cap = 256;
 };
 Tuning g_tune[PI_MAX_L + 1];
-std::map<std::pair<int, int>, int> g_occ;  // (device, Lk) -> resident workgroups per CU
+std::map<std::pair<int, int>, int> g_occ;  // (device, 2 Lk + by_value) -> workgroups per CU
 
 // Chunk length per lane: long runs amortize the per-chunk fold, but a small
 // query still has to fill every workgroup slot several times over. A query's
@@ -290,8 +290,11 @@ uint32_t run_cap_for(int Lk) {
   return g_tune[Lk].run_cap;
 }
 
-// Grid of a head launch for limb class Lk: CUs x workgroups per CU.
-int resident_grid(int Lk) {
+// Grid of a head launch for limb class Lk: CUs x workgroups per CU, from the
+// occupancy of the kernel instance that runs it (by_value: segment table in
+// the kernel arguments, one query; otherwise in device memory, batches and
+// serving steps).
+int resident_grid(int Lk, bool by_value) {
   const int cus = device_cus();
   if (cus <= 0) return 2048;
   int dev = 0;
@@ -305,13 +308,13 @@ int resident_grid(int Lk) {
     int occ = 0;
     {
       std::lock_guard<std::mutex> lk(g_mu);
-      auto it = g_occ.find({dev, Lk});
+      auto it = g_occ.find({dev, 2 * Lk + (by_value ? 1 : 0)});
       if (it != g_occ.end()) occ = it->second;
     }
     if (occ == 0) {
-      occ = std::max(1, head_occupancy(Lk));
+      occ = std::max(1, head_occupancy(Lk, by_value));
       std::lock_guard<std::mutex> lk(g_mu);
-      g_occ[{dev, Lk}] = occ;
+      g_occ[{dev, 2 * Lk + (by_value ? 1 : 0)}] = occ;
     }
     per = (uint32_t)occ;
   }
@@ -388,7 +391,7 @@ int run_single(const QueryPlan &qp, uint64_t *out, pi_status *status, uint32_t m
                hipStream_t st) {
   std::vector<HeadSeg> segs;
   head_segments(qp, 0, segs);
-  const int grid_max = resident_grid(qp.Lk);
+  const int grid_max = resident_grid(qp.Lk, true);
   const uint64_t nchunks =
       number_chunks(segs, pick_run(qp.nhead, grid_max, run_cap_for(qp.Lk)), 0);
   HeadSegTable tab;
@@ -443,13 +446,13 @@ int plan_batch(const pi_query *q, int count, BatchPlan *bp) {
       it = by_class.emplace(qp.Lk, (int)bp->cls.size()).first;
       bp->cls.emplace_back();
       bp->cls.back().Lk = qp.Lk;
-      bp->cls.back().grid = resident_grid(qp.Lk);
+      bp->cls.back().grid = resident_grid(qp.Lk, false);
     }
     ClassPlan &c = bp->cls[it->second];
     const uint32_t local = (uint32_t)c.fins.size();
     std::vector<HeadSeg> segs;
     head_segments(qp, local * 2u * (uint32_t)qp.Lk, segs);
-    const uint32_t cap = std::max(pick_run(qp.nhead, resident_grid(qp.Lk), run_cap_for(qp.Lk)),
+    const uint32_t cap = std::max(pick_run(qp.nhead, resident_grid(qp.Lk, false), run_cap_for(qp.Lk)),
                                   min_run_cap(qp.nhead));
     c.nchunks += number_chunks(segs, cap, c.nchunks);
     c.segs.insert(c.segs.end(), segs.begin(), segs.end());

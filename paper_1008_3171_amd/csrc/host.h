@@ -32,7 +32,7 @@ uint32_t run_cap_for(int Lk);
 uint32_t min_run_cap(uint64_t head_terms);
 FinQuery fin_query(const QueryPlan &qp, uint64_t out_off, uint32_t status_mode, uint32_t sidx,
                    uint32_t acc_off);
-int resident_grid(int Lk);
+int resident_grid(int Lk, bool by_value);
 int hip_err(hipError_t e);
 
 }  // namespace host

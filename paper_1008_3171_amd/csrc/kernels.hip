@@ -656,15 +656,16 @@ hipError_t launch_combine(const uint64_t *parts, int count, int Lq, uint32_t P, 
 }
 
 template <int L>
-static int occupancy_L() {
+static int occupancy_L(bool by_value) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, head_kernel_ptr<L>, 256, 0) != hipSuccess)
-    return 0;
-  return n;
+  const hipError_t e =
+      by_value ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, head_kernel_args<L>, 256, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, head_kernel_ptr<L>, 256, 0);
+  return e == hipSuccess ? n : 0;
 }
 
-int head_occupancy(int Lk) {
-#define C(L) occupancy_L<L>()
+int head_occupancy(int Lk, bool by_value) {
+#define C(L) occupancy_L<L>(by_value)
   switch (Lk) {
     case 1: return C(1);
     case 2: return C(2);

@@ -149,7 +149,7 @@ int pi_server_submit(pi_server *s, const pi_query *q, uint64_t tag) {
   s->free_slots.pop_back();
   a.tag = tag;
   head_segments(a.qp, a.slot * kSlotCounters, a.segs);
-  const uint32_t cap = std::max(pick_run(a.qp.nhead, resident_grid(a.qp.Lk), run_cap_for(a.qp.Lk)),
+  const uint32_t cap = std::max(pick_run(a.qp.nhead, resident_grid(a.qp.Lk, false), run_cap_for(a.qp.Lk)),
                                 min_run_cap(a.qp.nhead));
   a.nchunks = number_chunks(a.segs, cap, 0);
   s->active.push_back(std::move(a));
@@ -233,7 +233,7 @@ int pi_server_step(pi_server *s, uint32_t *finished) {
     const int Lk = kv.first;
     const uint64_t nch = chunks_by_class[Lk];
     if (!nch) continue;
-    const int grid = (int)std::min<uint64_t>(nch, (uint64_t)resident_grid(Lk));
+    const int grid = (int)std::min<uint64_t>(nch, (uint64_t)resident_grid(Lk, false));
     if (int e = hip_err(launch_head_ptr(Lk, s->dsegs + kv.second.first, (int)kv.second.second, nch,
                                         grid, s->acc, ctr + launch++, s->st)))
       return e;
