@@ -178,7 +178,8 @@ PI_API int pi_get_tuning(int limbs, uint32_t *wg_per_cu, uint32_t *run_cap);
  * successive squaring and Montgomery's method). Both modes compute the same
  * exact integers, so every result is bit-identical:
  *   PI_ARITH_FAST (default): moduli from 2^29 to 2^51 run on integer-valued
- *     binary64 numbers whose every operation is exact (fp64 FMA issues at the
+ *     binary64 numbers whose every operation is exact, for both the
+ *     exponentiation and the division into P bits (fp64 FMA issues at the
  *     same rate as a 32-bit integer multiply-add and needs fewer
  *     instructions); Montgomery below and above;
  *   PI_ARITH_INTEGER: integer Montgomery arithmetic for every modulus.

@@ -111,17 +111,6 @@ __device__ __forceinline__ double pow2_f64(uint32_t v, double M, double inv) {
   return __builtin_fma(-q, M, p);
 }
 
-// The residue in [0, M) as an integer, for |x| < M < 2^48 or |x| <= M/2 + 1
-// (M < 2^51): x * inv then lies strictly between -1 and 1 even after
-// rounding, so its floor is -1 or 0 and x - floor(x * inv) M is in [0, M).
-// Adding 2^52 to an integer-valued double in [0, 2^52) puts the integer in
-// the significand field.
-__device__ __forceinline__ uint64_t residue_u64(double x, double M, double inv) {
-#pragma clang fp contract(off)
-  const double r = __builtin_fma(-__builtin_floor(x * inv), M, x);
-  return (uint64_t)__double_as_longlong(r + 0x1p52) & ((1ull << 52) - 1u);
-}
-
 // -M^-1 mod 2^32, M odd. (3M) xor 2 is an inverse to 5 bits; each Newton step
 // x <- x(2 - Mx) doubles the number of correct low bits (5, 10, 20, 40).
 __device__ __forceinline__ uint32_t neg_inv32(uint32_t m) {
