@@ -4,10 +4,13 @@
 // P-bit division r*2^P/M. Both are done without any division instruction:
 //
 //  * modular exponentiation (section 4.2 names Montgomery's method for large
-//    moduli): a left-to-right binary ladder in Montgomery form. Each step is
-//    one Montgomery reduction of x^2 * 2^b, so the doubling for a 1 bit costs
-//    a shift, not a multiplication. The ladder's target exponent is chosen so
-//    that the Montgomery form of its result is already s = 2^(E+64L) mod M.
+//    moduli): a left-to-right ladder over exponent windows. In the integer
+//    classes each step is one Montgomery reduction of x^2 * 2^b, so the
+//    doubling for a 1 bit costs a shift, not a multiplication, and the
+//    ladder's target exponent is chosen so that the Montgomery form of its
+//    result is already s = 2^(E+64L) mod M. In the binary64 class the
+//    residues are plain (2^E mod M itself) and each step is exact fp64
+//    arithmetic.
 //  * division, integer classes: with s = r*2^(64L) mod M, the quotient
 //    t = floor(r*2^(64L)/M) satisfies t*M = r*2^(64L) - s, so
 //    t = -s * M^-1 mod 2^(64L). That is an exact (Hensel) division, limb by
@@ -16,7 +19,7 @@
 //    floor(r*2^P/M), so the P-bit term, left-aligned in L limbs, is t with its
 //    low 64L-P bits cleared.
 //  * division, binary64 class: schoolbook long division of r 2^P by M from
-//    the top, in signed digits of about 40 bits, each one exact fp64 FMA
+//    the top, in signed digits of up to 46 bits, each one exact fp64 FMA
 //    rounding and one exact fp64 FMA remainder; a lane sums its terms' digits
 //    per position in doubles and turns the sums into limbs once per run.
 //
