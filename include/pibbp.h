@@ -164,6 +164,29 @@ PI_API size_t pi_workspace_size(const pi_query *q, int count);
  * floor((n-1+c_j)/step)+1 where that is positive. Host-only arithmetic. */
 PI_API uint64_t pi_head_terms(int formula, uint64_t n);
 
+/* One head segment of a plan: series j, index range [kb, ke), the arithmetic
+ * of its moduli M = a_j k + b_j (cls: 22, 27, 29, 31: R = 2^32 Montgomery,
+ * M below 2^cls; 33, 42, 48, 51: exact binary64, M below 2^cls; 64:
+ * R = 2^62 Montgomery, M below 2^54), the indices each lane takes per chunk
+ * (run), its chunk count (chunks of 256 * run indices) and, for cls 64, the
+ * exponent bits folded into the ladder's start value (pre). */
+typedef struct {
+  uint32_t j, cls, run, pre;
+  uint64_t kb, ke, nchunks;
+} pi_segment;
+
+/* The head segments that pi_extract_ex (series_mask 0x7f, k0 = 0,
+ * k1 = UINT64_MAX) or pi_sum_slice (series_mask 1 << j) would launch for this
+ * query, under the current arithmetic mode and tuning: the partition of
+ * section 4 (jobs of series and modulus range, tasks of 256 * run indices)
+ * as this library plans it. Host work only; nothing is launched. Mask bits
+ * past the formula's series count are ignored. *count receives the number of
+ * segments; segs (host, max_segs entries) receives them, or PI_EINVAL is
+ * returned when max_segs is too small (count still set). Other errors as for
+ * pi_sum_slice. */
+PI_API int pi_plan_head(int formula, uint32_t series_mask, uint64_t n, uint64_t k0, uint64_t k1,
+                        uint32_t P, pi_segment *segs, int max_segs, int *count);
+
 /* Launch shape of the head kernel instance for `limbs` = ceil(P/64) rounded
  * up to an instantiated count (1-6, 8, 12, 17), or every instance when limbs
  * is 0: wg_per_cu workgroups per CU (0, the default: as many as fit, from the

@@ -18,6 +18,10 @@ BBP = 0
 BELLARD = 1
 PI_OK = 0
 PI_UNCERTAIN = 1
+PI_EINVAL = -1
+PI_ENOMEM = -2
+PI_EDEVICE = -3
+PI_EUNSUPPORTED = -4
 MAX_P = 1088
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -67,6 +71,8 @@ def load():
         lib.pi_workspace_size.restype = ctypes.c_size_t
         lib.pi_head_terms.argtypes = [i32, u64]
         lib.pi_head_terms.restype = u64
+        lib.pi_plan_head.argtypes = [i32, u32, u64, u64, u64, u32, vp, i32, vp]
+        lib.pi_plan_head.restype = i32
         lib.pi_strerror.argtypes = [i32]
         lib.pi_strerror.restype = ctypes.c_char_p
         lib.pi_shutdown.argtypes = []
@@ -152,6 +158,30 @@ def limbs(P: int) -> int:
 
 def head_terms(formula: int, n: int) -> int:
     return int(load().pi_head_terms(formula, n))
+
+
+class Segment(ctypes.Structure):
+    """pi_segment."""
+    _fields_ = [("j", ctypes.c_uint32), ("cls", ctypes.c_uint32), ("run", ctypes.c_uint32),
+                ("pre", ctypes.c_uint32), ("kb", ctypes.c_uint64), ("ke", ctypes.c_uint64),
+                ("nchunks", ctypes.c_uint64)]
+
+
+def plan_head(formula: int, n: int, P: int, k0: int = 0, k1: int = 2 ** 64 - 1,
+              series_mask: int = 0x7F) -> list:
+    """pi_plan_head: the head segments a query or slice would launch, as
+    dicts (host only)."""
+    lib = load()
+    count = ctypes.c_int(0)
+    rc = lib.pi_plan_head(formula, series_mask, n, k0, k1, P, None, 0, ctypes.byref(count))
+    if rc != PI_OK and count.value == 0:
+        raise PiError(rc, "pi_plan_head")
+    segs = (Segment * max(1, count.value))()
+    rc = lib.pi_plan_head(formula, series_mask, n, k0, k1, P, segs, count.value,
+                          ctypes.byref(count))
+    if rc != PI_OK:
+        raise PiError(rc, "pi_plan_head")
+    return [{f: getattr(segs[i], f) for f, _ in Segment._fields_} for i in range(count.value)]
 
 
 def extract(formula: int, n: int, nbits: int, P: int | None = None, out=None, status=None,

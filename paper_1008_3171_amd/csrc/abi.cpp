@@ -352,32 +352,38 @@ uint32_t safe_pre62(uint32_t run, uint64_t Mmin, uint64_t Mmax, uint64_t a) {
   return 0;
 }
 
-// Number the chunks of the segments and fix each segment's run: about a
-// quarter of the segment per lane-run column up to run_cap, and for class 62
-// no more than the starting-value bound allows.
+// Number the chunks of one query's segments and fix each segment's run: about
+// a quarter of the segment per lane-run column up to run_cap, and for the
+// run-quotient and class-62 starts no more than their start-value bounds
+// allow. Runs held down by those bounds add chunks, so the cap doubles until
+// the query has fewer than 2^31 chunks: its carry-save counters take one
+// value below 2^32 per chunk and stay exact below 2^32 of them.
 uint64_t number_chunks(std::vector<HeadSeg> &segs, uint32_t run_cap, uint64_t chunk_base) {
-  uint64_t nchunks = chunk_base;
-  for (HeadSeg &g : segs) {
-    const HostSeries &s = kHSeries[g.formula][g.j];
-    const uint64_t len = g.ke - g.kb;
-    uint32_t run = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(run_cap, len / 1024u));
-    g.pre = 0;
-    if (g.cls == 27 || g.cls == 29 || g.cls == 31) {
-      // the start value 2^32 - qM stays below 2M when 2^32 2a run < Mmin^2
-      const uint64_t Mmin = s.a * g.kb + s.b;
-      const uint64_t lim = (uint64_t)(((unsigned __int128)Mmin * Mmin >> 32) / (2u * s.a));
-      run = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(run, lim));
+  for (;;) {
+    uint64_t nchunks = chunk_base;
+    for (HeadSeg &g : segs) {
+      const HostSeries &s = kHSeries[g.formula][g.j];
+      const uint64_t len = g.ke - g.kb;
+      uint32_t run = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(run_cap, len / 1024u));
+      g.pre = 0;
+      if (g.cls == 27 || g.cls == 29 || g.cls == 31) {
+        // the start value 2^32 - qM stays below 2M when 2^32 2a run < Mmin^2
+        const uint64_t Mmin = s.a * g.kb + s.b;
+        const uint64_t lim = (uint64_t)(((unsigned __int128)Mmin * Mmin >> 32) / (2u * s.a));
+        run = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(run, lim));
+      }
+      if (g.cls == 64) {
+        const uint64_t Mmin = s.a * g.kb + s.b, Mmax = s.a * (g.ke - 1) + s.b;
+        run = std::max<uint32_t>(1, safe_run62(run, Mmin, Mmax, s.a));
+        g.pre = safe_pre62(run, Mmin, Mmax, s.a);
+      }
+      g.run = run;
+      g.chunk0 = nchunks;
+      nchunks += (len + 256ull * run - 1) / (256ull * run);
     }
-    if (g.cls == 64) {
-      const uint64_t Mmin = s.a * g.kb + s.b, Mmax = s.a * (g.ke - 1) + s.b;
-      run = std::max<uint32_t>(1, safe_run62(run, Mmin, Mmax, s.a));
-      g.pre = safe_pre62(run, Mmin, Mmax, s.a);
-    }
-    g.run = run;
-    g.chunk0 = nchunks;
-    nchunks += (len + 256ull * run - 1) / (256ull * run);
+    if (nchunks - chunk_base < (1ull << 31) || run_cap >= (1u << 30)) return nchunks - chunk_base;
+    run_cap *= 2;
   }
-  return nchunks - chunk_base;
 }
 
 // Smallest run cap that keeps a query below 2^31 chunks (its counters take one
@@ -560,6 +566,33 @@ uint64_t pi_head_terms(int formula, uint64_t n) {
   for (int j = 0; j < kHJ[formula]; ++j)
     tot += first_tail(kHSeries[formula][j], kHStep[formula], n - 1);
   return tot;
+}
+
+int pi_plan_head(int formula, uint32_t series_mask, uint64_t n, uint64_t k0, uint64_t k1,
+                 uint32_t P, pi_segment *segs, int max_segs, int *count) {
+  if (!count || max_segs < 0 || (max_segs > 0 && !segs)) return PI_EINVAL;
+  if (formula != PI_BBP && formula != PI_BELLARD) return PI_EINVAL;
+  QueryPlan qp;
+  if (int e = make_plan(formula, n, P, P, series_mask, k0, k1, &qp)) return e;
+  std::vector<HeadSeg> hs;
+  head_segments(qp, 0, hs);
+  number_chunks(hs, pick_run(qp.nhead, resident_grid(qp.Lk, true), run_cap_for(qp.Lk)), 0);
+  *count = (int)hs.size();
+  if ((int)hs.size() > max_segs) return PI_EINVAL;
+  for (size_t i = 0; i < hs.size(); ++i) {
+    const HeadSeg &g = hs[i];
+    const uint64_t next = i + 1 < hs.size() ? hs[i + 1].chunk0 : 0;
+    pi_segment &o = segs[i];
+    o.j = g.j;
+    o.cls = g.cls;
+    o.run = g.run;
+    o.pre = g.pre;
+    o.kb = g.kb;
+    o.ke = g.ke;
+    o.nchunks = i + 1 < hs.size() ? next - g.chunk0
+                                  : (g.ke - g.kb + 256ull * g.run - 1) / (256ull * g.run);
+  }
+  return PI_OK;
 }
 
 }  // extern "C"
