@@ -345,16 +345,19 @@ __device__ __forceinline__ void hensel_d32(uint64_t s, uint64_t M, uint32_t mp32
   }
 }
 
-// The same with 32-bit limbs, for class-32 moduli (mp32 = -M^-1 mod 2^32).
+// The same with 32-bit digits, for class-32 moduli (M < 2^31,
+// mp32 = -M^-1 mod 2^32). Digit u = h * mp32 makes h + uM divisible by 2^32;
+// h + uM < 2^63, so one v_mad_u64_u32 forms it exactly and its high word is
+// the next h, again below M: two instructions per digit.
 template <int L>
 __device__ __forceinline__ void hensel32(uint32_t s, uint32_t M, uint32_t mp32, uint64_t (&t)[L]) {
   uint32_t h = s;
 #pragma unroll
   for (int i = 0; i < L; ++i) {
-    uint32_t lo = h * mp32;
-    h = __umulhi(lo, M) + (h != 0u ? 1u : 0u);
-    uint32_t hi = h * mp32;
-    h = __umulhi(hi, M) + (h != 0u ? 1u : 0u);
+    const uint32_t lo = h * mp32;
+    h = (uint32_t)(mad64(lo, M, h) >> 32);
+    const uint32_t hi = h * mp32;
+    if (i + 1 < L) h = (uint32_t)(mad64(hi, M, h) >> 32);
     t[i] = ((uint64_t)hi << 32) | lo;
   }
 }

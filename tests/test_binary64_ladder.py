@@ -117,6 +117,29 @@ def test_hensel_digit_recurrence():
         assert t == (-s * pow(M, -1, 2 ** (64 * L))) % 2 ** (64 * L)
 
 
+
+def test_hensel32_digit_recurrence():
+    # 32-bit-digit Hensel division for moduli below 2^31: u = h * (-M^-1 mod
+    # 2^32) mod 2^32, then h' = (h + uM) / 2^32 from one 64-bit multiply-add:
+    # h + uM stays below 2^63, is divisible by 2^32, and h' stays below M;
+    # the digits are -s M^-1 mod 2^(64L)
+    rng = random.Random(32)
+    for _ in range(3000):
+        bits = rng.choice([2, 3, 20, 22, 27, 29, 30, 31])
+        M = rng.getrandbits(bits) | 1 | (1 << (bits - 1))
+        s = rng.choice([0, 1, M - 1, rng.randrange(M)])
+        L = rng.choice([1, 2, 3, 5, 17])
+        mp = (-pow(M, -1, 2 ** 32)) % 2 ** 32
+        h, t = s, 0
+        for i in range(2 * L):
+            u = (h * mp) % 2 ** 32
+            A = h + u * M
+            assert A < 2 ** 63 and A % 2 ** 32 == 0
+            h = A >> 32
+            assert h < M
+            t |= u << (32 * i)
+        assert t == (-s * pow(M, -1, 2 ** (64 * L))) % 2 ** (64 * L)
+
 # limb counts the kernels are built for; a query of P bits uses the smallest
 # that holds it
 LIMB_CLASSES = [1, 2, 3, 4, 5, 6, 8, 12, 17]
