@@ -97,9 +97,9 @@ def _pre_bits(run, Mmin, Mmax, a):
 #   (name, first modulus, W, per squaring, per window, per term, offset)
 # (binary64 per term at L = 5: seven 46-bit digits of 5 instructions each.)
 KERNEL_CLASSES = [
-    ("22", 0, 3, 3, 2, 75, -32),        # R = 2^32 Montgomery, doubling start
-    ("27", 2 ** 22, 2, 3, 2, 67, -32),  # R = 2^32, run-quotient start
-    ("29", 2 ** 27, 1, 3, 2, 67, -32),  # R = 2^32, run-quotient start
+    ("22", 0, 3, 3, 2, 70, -32),        # R = 2^32 Montgomery, doubling start
+    ("27", 2 ** 22, 2, 3, 2, 62, -32),  # R = 2^32, run-quotient start
+    ("29", 2 ** 27, 1, 3, 2, 62, -32),  # R = 2^32, run-quotient start
     ("f4", 2 ** 29, 4, 6, 2, 49, 0),    # binary64
     ("f3", 2 ** 33, 3, 6, 2, 48, 0),
     ("f2", 2 ** 42, 2, 6, 2, 47, 0),
