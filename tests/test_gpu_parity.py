@@ -222,9 +222,11 @@ def test_table_2_2_row_m12_full_size():
     assert head < N <= head + 7 * (320 // 10 + 2)
 
 
-@pytest.mark.parametrize("m", [9, 10, 11])
+@pytest.mark.parametrize("m", [9, 10, 11, 12])
 def test_table_2_2_rows_all_printed_bits(m):
-    # the paper's wide rows (1000, 1000 and 996 bits) at P = 1088: 17 limbs
+    # the paper's wide rows (1000, 1000, 996 and 1000 bits) at P = 1088: 17
+    # limbs; m = 12 sums 7*10^11 head terms through the 24-digit binary64
+    # division
     row = [r for r in read_golden("table_2_2.txt") if r[0] == str(m)][0]
     n, nbits = int(row[1]), int(row[2])
     S, N, cert = gpu_extract(pb.BELLARD, n, nbits, 1088)
