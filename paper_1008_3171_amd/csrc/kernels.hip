@@ -203,7 +203,7 @@ __device__ __forceinline__ void lane_run62(uint64_t k0, uint32_t run, uint32_t p
 }
 
 // Binary64 terms of one lane, 2^29 <= M < 2^51: r = 2^E mod M by a
-// left-to-right ladder over W-bit windows (W squarings, the
+// left-to-right ladder over the bits of X = E in W-bit windows (W squarings, the
 // window's value folded into the last one as a power of two); W = 4 for
 // M < 2^33, 3 for M < 2^42, 2 for M < 2^48, and from there W = 2 with a
 // second reduction after each window (kRe). The top t = min(6, bitlen X) bits v of X
