@@ -90,8 +90,9 @@ def _pre_bits(run, Mmin, Mmax, a):
 # (binary64: the top 6; class 62: `pre`; class 32: none). X is E for the
 # binary64 classes and E + 64L + offset for the integer ones, whose Hensel
 # division needs 2^(64L) r. Each of the remaining r bits costs one squaring,
-# each whole W-bit window 2 more (exponent digit, scale) and a short leading
-# window (r mod W bits) 3 more. The per-term part covers the start value, the
+# each whole W-bit window its digit (2 instructions when folded into the last
+# squaring, 5 when applied after it) and a short leading window (r mod W
+# bits) one more than a whole one, for its 64-bit shift. The per-term part covers the start value, the
 # reciprocal or the 32-bit inverse and the division at L = 5 (binary64: long
 # division; integer: Hensel, mask and accumulation).
 #   (name, first modulus, W, per squaring, per window, per term, offset)
@@ -103,7 +104,7 @@ KERNEL_CLASSES = [
     ("f4", 2 ** 29, 4, 6, 2, 49, 0),    # binary64
     ("f3", 2 ** 33, 3, 6, 2, 48, 0),
     ("f2", 2 ** 42, 2, 6, 2, 47, 0),
-    ("fr", 2 ** 48, 2, 6, 5, 47, 0),    # binary64, second reduction per window
+    ("fs", 2 ** 48, 5, 6, 5, 47, 0),    # binary64, digit applied after the squarings
     ("62", 2 ** 51, 1, 16, 0, 104, -62),  # R = 2^62, two 31-bit digits
 ]
 # The binary64 classes also take a carry step over each lane's digit sums
@@ -116,7 +117,7 @@ def _term_ops(cls, W, per_sq, per_win, fixed, nb, pre):
     start = 6 if cls[0] == "f" else (pre if cls == "62" else 0)
     r = max(0, nb - start)
     flush = FP_EXTRA_PER_TERM if cls[0] == "f" else 0.0
-    return fixed + flush + per_sq * r + per_win * (r // W) + (3 if r % W else 0)
+    return fixed + flush + per_sq * r + per_win * (r // W) + (per_win + 1 if r % W else 0)
 
 
 def valu_ops_per_launch(formula, n, P, run=64):

@@ -102,7 +102,8 @@ std::atomic<int> g_arith{PI_ARITH_FAST};
 //    three-bit windows), [2^22, 2^27) and [2^27, 2^29) (R = 2^32, run-quotient
 //    start, two- and one-bit windows), [2^29, 2^33), [2^33, 2^42) and
 //    [2^42, 2^48) (binary64 with four-, three- and two-bit windows),
-//    [2^48, 2^51) (binary64, two-bit windows, a second reduction per window)
+//    [2^48, 2^51) (binary64, five-bit windows, each digit applied after the
+//    window's squarings)
 //    and from 2^51 (R = 2^62).
 //  * PI_ARITH_INTEGER: the same below 2^29, [2^29, 2^31) (R = 2^32, reduced
 //    residues), then R = 2^62 split at 2^36 so that the small moduli, where a

@@ -28,8 +28,8 @@
 //  * binary64 (2^29 <= M < 2^51): plain (not Montgomery) residues held
 //    exactly in doubles; a squaring is six full-rate fp64 instructions
 //    against sixteen integer ones for the same modulus in class 62, exponent
-//    windows of up to four bits cost two more per window, and from 2^48 a
-//    second reduction per window three more;
+//    windows of up to four bits cost two more per window, and from 2^48
+//    five-bit windows apply their digit after the squarings, five more;
 //  * class 62 (2^51 <= M < 2^54): R = 2^62, residues in two 31-bit digits,
 //    kept below 8M;
 //  * R = 2^64 with residues below 2M (M < 2^60): the few tail terms.
@@ -59,10 +59,11 @@ namespace pibbp {
 // 2^-75, so |y| <= M/2 + kappa H with kappa = 3 * 2^-53 (inv, the rounding of
 // H inv, and Lo each 2^-53). Two-bit windows then keep |x| <= 0.75 M below
 // 2^48: from 0.75 M the first squaring gives at most 0.553 M and the second
-// (d <= 3) at most 0.73 M. From 2^48 to 2^51 a second reduction follows each
-// window: from |x| <= M/2 + 2 the first squaring gives at most 0.69 M, the
-// second at most 3.35 M (below 2^53, so still exact), and the reduction
-// returns |x| <= M/2 + 2.
+// (d <= 3) at most 0.73 M. From 2^48 to 2^51 a window is five plain
+// squarings and then its digit on its own (scale_f64): from
+// |x| <= M (1/2 + 2^-20) the squarings give at most 0.69, 0.86, 1.05, 1.33 and
+// 1.82 M (every value below 2^53, so still exact), and 2^d y with d <= 31 is
+// reduced by one rounded quotient (below 2^33) back to |x| <= M (1/2 + 2^-20).
 
 // One Newton step toward 1/m from r: relative error e becomes e^2 + 2^-53.
 // From 1/(M - 2a), at most 2^-26.6 away for M >= 2^31 and a <= 10, one step
@@ -97,12 +98,16 @@ __device__ __forceinline__ double sqr_f64(double x, double M, double inv) {
   return __builtin_fma(-q, M, h) + lo;
 }
 
-// The second reduction r - rint(r * inv) M: three instructions that bring
-// any |r| < 2^53 back to |r| <= M/2 + 2.
-__device__ __forceinline__ double rereduce_f64(double r, double M, double inv) {
+// A window's digit applied on its own: 2^d y - rint(2^d y inv) M. For
+// |y| <= 1.82 M, M < 2^51 and d <= 31, 2^d y / M is below 2^33 in magnitude
+// and 2^d y inv is within 2^-20 of it, so the result is exact and at most
+// M (1/2 + 2^-20) in magnitude. Five instructions with the digit's
+// extraction.
+__device__ __forceinline__ double scale_f64(double y, int d, double M, double inv) {
 #pragma clang fp contract(off)
-  const double q = __builtin_rint(r * inv);
-  return __builtin_fma(-q, M, r);
+  const double ys = __builtin_amdgcn_ldexp(y, d);
+  const double q = __builtin_rint(ys * inv);
+  return __builtin_fma(-q, M, ys);
 }
 
 // 2^v mod M, |result| < M, for v < 64 and M >= 2^29: the error term

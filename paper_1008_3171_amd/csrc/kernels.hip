@@ -205,8 +205,8 @@ __device__ __forceinline__ void lane_run62(uint64_t k0, uint32_t run, uint32_t p
 // Binary64 terms of one lane, 2^29 <= M < 2^51: r = 2^E mod M by a
 // left-to-right ladder over the bits of X = E in W-bit windows (W squarings, the
 // window's value folded into the last one as a power of two); W = 4 for
-// M < 2^33, 3 for M < 2^42, 2 for M < 2^48, and from there W = 2 with a
-// second reduction after each window (kRe). The top t = min(6, bitlen X) bits v of X
+// M < 2^33, 3 for M < 2^42, 2 for M < 2^48, and from there W = 5 with the
+// window's value applied after its squarings as its own step (kSep). The top t = min(6, bitlen X) bits v of X
 // give the start 2^v mod M directly; the remaining bits begin with one short
 // window (their count mod W) and then whole windows at multiples of W. The
 // whole windows above bit S = 32 - (32 mod W) are read from X >> S and the
@@ -216,7 +216,7 @@ __device__ __forceinline__ void lane_run62(uint64_t k0, uint32_t run, uint32_t p
 // floor(r 2^P / M) is then divided out in binary64 digits (fp_term_digits),
 // summed per digit position (with a carry step every kFpCarryTerms terms) and
 // added to sum at the end of the run.
-template <int L, int W, bool kRe, int kNewton>
+template <int L, int W, bool kSep, int kNewton>
 __device__ __forceinline__ void lane_runf(uint64_t k0, uint32_t run, uint64_t kend, uint64_t a,
                                           uint64_t b, uint64_t dc, uint64_t step, uint32_t P,
                                           uint64_t (&sum)[L]) {
@@ -249,9 +249,9 @@ __device__ __forceinline__ void lane_runf(uint64_t k0, uint32_t run, uint64_t ke
       const int lead = rest % W, top = rest - lead;
       double x = pow2_f64((uint32_t)(X >> rest), Md, inv);
       auto sq = [&](double y) { return sqr_f64(y, Md, inv); };
-      auto sqd = [&](double y, uint32_t dg) {  // a window's last squaring
-        y = sqr_f64(y, (int)dg, Md, inv);
-        return kRe ? rereduce_f64(y, Md, inv) : y;
+      auto sqd = [&](double y, uint32_t dg) {  // a window's last squaring and its digit
+        return kSep ? scale_f64(sqr_f64(y, Md, inv), (int)dg, Md, inv)
+                    : sqr_f64(y, (int)dg, Md, inv);
       };
       if (lead) {
         for (int j = 1; j < lead; ++j) x = sq(x);
@@ -372,7 +372,7 @@ __device__ void head_chunks(const HeadSeg *segs, int nseg, uint64_t nchunks,
     for (int i = 0; i < L; ++i) sum[i] = 0;
     switch (sg.cls) {
       case 64: lane_run62<L>(k0, run, sg.pre, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
-      case 51: lane_runf<L, 2, true, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+      case 51: lane_runf<L, 5, true, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
       case 48: lane_runf<L, 2, false, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
       case 42: lane_runf<L, 3, false, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
       case 33: lane_runf<L, 4, false, 2>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;

@@ -12,9 +12,11 @@
  * where ok is 1 when both intermediate results were below 2^53 in magnitude
  * (so exact) and |y| < M.
  * "W M W d x re inv_mode" lines run one W-bit window with digit d from x and
- * print "y ok" (ok: every intermediate below 2^53). "L M X W re steps" lines
- * print the full ladder's 2^X mod M (steps: Newton steps per modulus, as in
- * inv_mode).
+ * print "y ok" (ok: every intermediate below 2^53). re 0: the digit goes into
+ * the window's last squaring; 1: the same, then a second reduction; 2: W
+ * plain squarings, then the digit applied on its own as 2^d y reduced by one
+ * rounded quotient. "L M X W re steps" lines print the full ladder's
+ * 2^X mod M (steps: Newton steps per modulus, as in inv_mode).
  * "D M x P B N inv_mode" lines divide x 2^P by M in N signed digits, most
  * significant first: ne = ceil(P / B) digits of B bits, the top one holding
  * P - (ne - 1)B, and 0-bit digits above it. Each digit is
@@ -39,6 +41,8 @@ static double inverse(double M, int mode) {
   return mode == 1 ? r : newton(M, r);
 }
 
+/* re 0: ok also needs |y| < M; re 1: a second reduction follows; re 2:
+ * only exactness is asked (the result may exceed M). */
 static int step(double x, int d, double M, double inv, int re, double *out) {
   const double xs = ldexp(x, d);
   const double h = x * xs;
@@ -47,14 +51,30 @@ static int step(double x, int d, double M, double inv, int re, double *out) {
   const double r0 = fma(-q, M, h);
   double y = r0 + lo;
   int ok = fabs(r0) < 0x1p53 && fabs(y) < 0x1p53;
-  if (re) y = fma(-rint(y * inv), M, y);
+  if (re == 1) y = fma(-rint(y * inv), M, y);
   *out = y;
   return ok && (re || fabs(y) < M);
 }
 
-/* One W-bit window: W - 1 plain squarings and one with the digit d, then the
- * second reduction when re; ok when every intermediate stayed exact. */
+/* The digit applied on its own: y = 2^d x - rint(2^d x * inv) M. ok when the
+ * quotient is an exact integer (below 2^52) and the result is exact. */
+static int scale(double x, int d, double M, double inv, double *out) {
+  const double xs = ldexp(x, d);
+  const double q = rint(xs * inv);
+  const double y = fma(-q, M, xs);
+  *out = y;
+  return fabs(q) < 0x1p52 && fabs(y) < 0x1p53;
+}
+
+/* One W-bit window. re 0: W - 1 plain squarings and one with the digit d;
+ * re 1: the same, then a second reduction; re 2: W plain squarings, then the
+ * digit applied on its own (scale). ok when every intermediate stayed exact. */
 static int window(double x, int W, int d, double M, double inv, int re, double *out) {
+  if (re == 2) {
+    for (int j = 0; j < W; ++j)
+      if (!step(x, 0, M, inv, 2, &x)) return 0;
+    return scale(x, d, M, inv, out);
+  }
   for (int j = 1; j < W; ++j)
     if (!step(x, 0, M, inv, 0, &x)) return 0;
   return step(x, d, M, inv, re, out);

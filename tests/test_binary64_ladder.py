@@ -25,11 +25,18 @@ import pytest
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-# (window bits W, lowest modulus, first modulus past the class, second
-# reduction after each window, Newton steps per modulus, invariant: |x| <= c M
-# between windows, plus 2 with the second reduction)
-CLASSES = [(4, 2 ** 29, 2 ** 33, False, 2, 1.0), (3, 2 ** 33, 2 ** 42, False, 1, 1.0),
-           (2, 2 ** 42, 2 ** 48, False, 1, 0.75), (2, 2 ** 48, 2 ** 51, True, 1, 0.5)]
+# (window bits W, lowest modulus, first modulus past the class, how a window
+# applies its digit, Newton steps per modulus, invariant: |x| <= c M between
+# windows). Digit modes: 0, in the window's last squaring; 2, after W plain
+# squarings as its own scale-and-reduce step, which leaves |x| <= M/2 + M/2^20.
+CLASSES = [(4, 2 ** 29, 2 ** 33, 0, 2, 1.0), (3, 2 ** 33, 2 ** 42, 0, 1, 1.0),
+           (2, 2 ** 42, 2 ** 48, 0, 1, 0.75), (5, 2 ** 48, 2 ** 51, 2, 1, 0.5)]
+
+
+def invariant(M, re, c):
+    if re == 2:
+        return M // 2 + (M >> 20)
+    return min(int(c * M), M - 1)
 
 
 @pytest.fixture(scope="module")
@@ -61,21 +68,19 @@ def test_window_keeps_the_invariant(model, W, lo, hi, re, steps, c):
     rng = random.Random(W * 100 + hi.bit_length())
     cases = []
     for M in edge_moduli(lo, hi, rng):
-        bound = int(c * M) + (2 if re else 0)
-        if not re:
-            bound = min(bound, M - 1)
+        bound = invariant(M, re, c)
         xs = [bound, -bound, bound - 1, -(bound - 7), 1, -1] + \
              [rng.randrange(-bound, bound + 1) for _ in range(8)]
         for x in xs:
             for d in range(1 << W):
                 for mode in (0, steps):
                     cases.append((M, d, x, mode))
-    out = model(["W %d %d %d %d %d %d" % (M, W, d, x, int(re), mode) for M, d, x, mode in cases])
+    out = model(["W %d %d %d %d %d %d" % (M, W, d, x, re, mode) for M, d, x, mode in cases])
     for (M, d, x, mode), line in zip(cases, out):
         y, ok = (int(v) for v in line.split())
         assert ok == 1, (M, d, x, mode)
         assert (y - (pow(x, 2 ** W, M) << d)) % M == 0, (M, d, x, mode)
-        assert abs(y) <= (int(c * M) + 2 if re else min(int(c * M), M - 1)), (M, d, x, y)
+        assert abs(y) <= invariant(M, re, c), (M, d, x, y)
 
 
 @pytest.mark.parametrize("W,lo,hi,re,steps,c", CLASSES)
@@ -87,7 +92,7 @@ def test_ladder_equals_pow(model, W, lo, hi, re, steps, c):
             X = rng.getrandbits(rng.randrange(1, 62)) | 1
             cases.append((M, X))
         cases += [(M, 1), (M, 63), (M, 64), (M, 2 ** 61 - 1), (M, 2 ** 61 + 12345)]
-    out = model(["L %d %d %d %d %d" % (M, X, W, int(re), steps) for M, X in cases])
+    out = model(["L %d %d %d %d %d" % (M, X, W, re, steps) for M, X in cases])
     for (M, X), line in zip(cases, out):
         assert int(line) == pow(2, X, M), (M, X, W, re)
 
@@ -167,7 +172,7 @@ def test_long_division_gives_the_truncated_term(model, W, lo, hi, re, steps, c):
           400, 512, 600, 768, 800, 1000, 1088]
     cases = []
     for M in edge_moduli(lo, hi, rng)[:9]:
-        bound = min(int(c * M) + (2 if re else 0), M - 1)
+        bound = invariant(M, re, c)
         for x in (bound, -bound, 0, 1, -1, M // 2, -(M // 2), rng.randrange(-bound, bound + 1)):
             for P in Ps:
                 cases.append((M, x, P, steps))

@@ -69,8 +69,8 @@ def test_slices_across_every_modulus_class_boundary(cut):
     # the head kernel switches arithmetic where the modulus reaches 2^22, 2^27
     # and 2^29 (32-bit Montgomery with three-, two- and one-bit windows),
     # 2^33, 2^42, 2^48 and 2^51 (binary64 windows of four, three and two bits,
-    # two bits with a second reduction per window, then R = 2^62); 2^31 and
-    # 2^46 are former cuts, kept as inner points:
+    # five bits with the digit applied after the squarings, then R = 2^62);
+    # 2^31 and 2^46 are former cuts, kept as inner points:
     # ranges straddling each cut for every series, with exponents just past
     # the cut and near 2^61 (both halves of a 64-bit exponent)
     rng = random.Random(5 + cut)
