@@ -250,7 +250,7 @@ int pio_sum_slice(int formula, int j, uint64_t d, uint64_t k0, uint64_t k1, uint
  * frac(2^d pi) lies within B = N + 2J units of S/2^P (modulo 1). With
  * G = S mod 2^(P-w), every number in that window has the same top w bits as S
  * exactly when G >= B and G + B <= 2^(P-w). */
-static int certify(const uint32_t *S, uint32_t P, uint32_t w, uint64_t B) {
+int pio_certify(const uint32_t *S, uint32_t P, uint32_t w, uint64_t B) {
   uint32_t gb = P - w;                      /* guard bits */
   uint32_t nw = nwords(P) + 1;
   uint32_t *G = (uint32_t *)calloc(nw, sizeof(uint32_t));
@@ -299,7 +299,7 @@ int pio_extract(int formula, uint64_t n, uint32_t w, uint32_t P, uint32_t *S, ui
   }
   free(part);
   if (N) *N = total;
-  if (certified) *certified = certify(S, P, w, total + 2u * (uint64_t)J);
+  if (certified) *certified = pio_certify(S, P, w, total + 2u * (uint64_t)J);
   return 0;
 }
 

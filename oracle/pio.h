@@ -49,6 +49,14 @@ int pio_sum_slice(int formula, int j, uint64_t d, uint64_t k0, uint64_t k1, uint
 int pio_extract(int formula, uint64_t n, uint32_t w, uint32_t P, uint32_t *S,
                 uint64_t *N, int32_t *certified, int nthreads);
 
+/* The certification test of pio_extract on its own (section 3.1, adapted to
+ * truncated terms): S is a P-bit sum (ceil(P/32) words), B the error bound in
+ * units of 2^-P. Returns 1 when every real number within B units of S
+ * (exclusive, modulo 2^P) has the same top w bits as S, i.e. when
+ * G >= B and G + B <= 2^(P-w) for the guard window G = S mod 2^(P-w);
+ * 0 otherwise. Requires 1 <= w <= P and B < 2^64. */
+int pio_certify(const uint32_t *S, uint32_t P, uint32_t w, uint64_t B);
+
 /* floor(frac(pi) * 2^nbits) by Machin's formula; out: ceil(nbits/32) words.
  * Returns 0 when the guard bits prove every output bit, -1 otherwise. */
 int pio_machin(uint32_t nbits, uint32_t *out);
