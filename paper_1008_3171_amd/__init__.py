@@ -156,6 +156,31 @@ def limbs(P: int) -> int:
     return (P + 63) // 64
 
 
+def _check(t, name: str, dtype, need: int):
+    """A caller's buffer must be a contiguous device tensor of `dtype` with at
+    least `need` elements: the kernels write through its raw pointer, so a
+    host tensor or a short buffer would be written out of bounds."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise ValueError("%s must be a torch tensor" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be on the GPU (got device %s)" % (name, t.device))
+    if t.dtype != dtype:
+        raise ValueError("%s must be %s (got %s)" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.numel() < need:
+        raise ValueError("%s holds %d elements; the call writes %d" % (name, t.numel(), need))
+
+
+def _check_limbs(out, P: int, name: str = "out"):
+    _check(out, name, _torch().int64, limbs(P))
+
+
+def _check_status(status, count: int = 1):
+    _check(status, "status", _torch().int32, 4 * count)
+
+
 def head_terms(formula: int, n: int) -> int:
     return int(load().pi_head_terms(formula, n))
 
@@ -196,6 +221,8 @@ def extract(formula: int, n: int, nbits: int, P: int | None = None, out=None, st
         out = torch.zeros(limbs(P), dtype=torch.int64, device="cuda")
     if status is None:
         status = torch.zeros(4, dtype=torch.int32, device="cuda")
+    _check_limbs(out, P)
+    _check_status(status)
     rc = lib.pi_extract_ex(formula, n, nbits, P, ctypes.c_void_p(out.data_ptr()),
                            ctypes.c_void_p(status.data_ptr()), _stream(stream))
     if rc != 0:
@@ -209,6 +236,7 @@ def extract_default(formula: int, n: int, nbits: int, out=None, stream=None):
     lib = load()
     if out is None:
         out = torch.zeros(limbs(nbits + 64), dtype=torch.int64, device="cuda")
+    _check_limbs(out, nbits + 64)
     rc = lib.pi_extract(formula, n, nbits, ctypes.c_void_p(out.data_ptr()), _stream(stream))
     if rc != 0:
         raise PiError(rc, "pi_extract")
@@ -221,6 +249,7 @@ def sum_slice(term: int, n: int, k0: int, k1: int, P: int, out=None, stream=None
     lib = load()
     if out is None:
         out = torch.zeros(limbs(P), dtype=torch.int64, device="cuda")
+    _check_limbs(out, P)
     rc = lib.pi_sum_slice(term, n, k0, k1, P, ctypes.c_void_p(out.data_ptr()), _stream(stream))
     if rc != 0:
         raise PiError(rc, "pi_sum_slice")
@@ -253,8 +282,15 @@ def extract_batch(qarr, count: int, out, status=None, workspace=None, stream=Non
     lib = load()
     if status is None:
         status = torch.zeros(4 * max(1, count), dtype=torch.int32, device="cuda")
+    if count < 0 or count > len(qarr):
+        raise ValueError("count %d outside the query array's %d entries" % (count, len(qarr)))
+    need = max([qarr[i].out_offset + limbs(qarr[i].P) for i in range(count)], default=0)
+    _check(out, "out", torch.int64, need)
+    if status is not False:
+        _check_status(status, count)
     ws_ptr, ws_bytes = None, 0
     if workspace is not None:
+        _check(workspace, "workspace", workspace.dtype, 0)
         ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
     st_ptr = None if status is False else status.data_ptr()
     rc = lib.pi_extract_batch(ctypes.cast(qarr, ctypes.c_void_p), count,
@@ -385,6 +421,8 @@ def sum_slice_ex(term: int, n: int, k0: int, k1: int, P: int, out=None, status=N
         out = torch.zeros(limbs(P), dtype=torch.int64, device="cuda")
     if status is None:
         status = torch.zeros(4, dtype=torch.int32, device="cuda")
+    _check_limbs(out, P)
+    _check_status(status)
     rc = lib.pi_sum_slice_ex(term, n, k0, k1, P, ctypes.c_void_p(out.data_ptr()),
                              ctypes.c_void_p(status.data_ptr()), _stream(stream))
     if rc != 0:
@@ -405,6 +443,11 @@ def combine(parts, count: int, P: int, nbits: int, nseries: int, nterms: int, ou
         out = torch.zeros(limbs(P), dtype=torch.int64, device="cuda")
     if status is None:
         status = torch.zeros(4, dtype=torch.int32, device="cuda")
+    if count < 0:
+        raise ValueError("count must be >= 0")
+    _check(parts, "parts", torch.int64, count * limbs(P))
+    _check_limbs(out, P)
+    _check_status(status)
     rc = lib.pi_combine(ctypes.c_void_p(parts.data_ptr()), count, P, nbits, nseries, nterms,
                         ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(status.data_ptr()),
                         _stream(stream))
@@ -425,6 +468,13 @@ class BatchPlan:
         lib.pi_batch_launch.restype = ctypes.c_int
         lib.pi_batch_destroy.argtypes = [vp]
         self._lib = lib
+        if count <= 0 or count > len(qarr):
+            raise ValueError("count %d outside the query array's %d entries" % (count, len(qarr)))
+        torch = _torch()
+        need = max(qarr[i].out_offset + limbs(qarr[i].P) for i in range(count))
+        _check(out, "out", torch.int64, need)
+        if status is not None:
+            _check_status(status, count)
         self.out, self.status = out, status
         h = vp()
         rc = lib.pi_batch_create(ctypes.cast(qarr, vp), count, vp(out.data_ptr()),
