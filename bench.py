@@ -9,8 +9,15 @@ themselves; nothing is read from disk.
 
 Prints one JSON line. `value` = head terms per second of the timed steps.
 `roofline` prices the head kernel's data-path instructions against the
-chip's VALU issue rate; `cpu_baseline` is the oracle on a bounded seeded sub-slice of the same
-workload.
+chip's VALU issue rate, next to the counter-derived figures of the committed
+profile and the int32-multiply fraction of the algorithmic multiply count;
+`cpu_baseline` is the oracle on a bounded seeded sub-slice of the same
+workload, on every host core this process may use.
+
+The arithmetic: exact binary64 (integer-valued doubles, every operation
+proven exact) for moduli from 2^29 to 2^51 plus 32- and 64-bit integers,
+hence `dtype` "binary64-exact+u32/u64"; `integer_only` repeats the query with
+integer Montgomery arithmetic for every modulus (dtype "u32/u64").
 """
 from __future__ import annotations
 
@@ -30,6 +37,9 @@ sys.path.insert(0, ROOT)
 PEAK_VALU = 256 * 64 * 2.4e9
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "head_kernel_bellard_n1e12_P320_traffic.json")
+# SQ_INSTS_VALU of the headline head kernel, per arithmetic mode, from
+# rocprofv3 --pmc runs of this script (profiles/head_kernel_*_counters.md)
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "head_kernel_bellard_n1e12_P320_counters.json")
 # the head kernel's device code and the planner that sizes its chunks (the
 # chunk count sets the scheduler's atomics, hence the write traffic)
 KERNEL_SOURCES = ["kernels.hip", "arith.h", "plan.h", "abi.cpp", "host.h"]
@@ -58,6 +68,20 @@ def measured_traffic():
     if t.get("kernel_source_sha256") != kernel_source_hash():
         return None
     return t["fetch_kib"] * 1024 * t["fetch_factor"] + t["write_kib"] * 1024 * t["write_factor"]
+
+
+def measured_counters(arith):
+    """VALU wave instructions per launch of the headline head kernel in one
+    arithmetic mode ("fast" or "integer"), from the committed counter runs;
+    None when the kernel sources changed after they were taken."""
+    try:
+        with open(COUNTERS_FILE) as f:
+            c = json.load(f)
+    except OSError:
+        return None
+    if c.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return c.get(arith)
 
 
 def series(formula):
@@ -160,11 +184,69 @@ def valu_ops_per_launch(formula, n, P, run=64):
     return int(round(total)), terms
 
 
+def mul32_per_launch(formula, n, P):
+    """The algorithmic 32-bit multiply count of every head term of one
+    extraction, as the work unit of the int32-multiply roofline: a term with
+    exponent E is bitlen(E) - 1 modular squarings of a 64-bit residue at 10
+    32-bit multiplies each (four partial products and six for the reduction),
+    16 for -M^-1 mod 2^64, and 7 per limb of the L-limb division, less 4
+    saved at the ends. Returns (multiplies, head terms)."""
+    rows, step = series(formula)
+    L = (P + 63) // 64
+    d = n - 1
+    total = terms = 0
+    for c, a, b in rows:
+        if d + c < 0:
+            continue
+        K = (d + c) // step + 1
+        k = 0
+        while k < K:
+            E = d + c - step * k
+            bl = E.bit_length()
+            lowE = 1 << (bl - 1) if bl > 0 else 0
+            kmax = min(K - 1, (d + c - lowE) // step) if bl > 0 else K - 1
+            cnt = kmax - k + 1
+            total += cnt * (10 * max(bl - 1, 0) + 16 + 7 * L - 4)
+            terms += cnt
+            k = kmax + 1
+    return total, terms
+
+
+def host_cores():
+    """(threads to use, what the host shows): the CPUs this process may run
+    on, further capped by a cgroup CPU quota when one is set, with nproc and
+    the CPU model."""
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    quota = None
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as f:
+            q, per = f.read().split()
+        if q != "max":
+            quota = max(1, int(int(q) / int(per)))
+    except (OSError, ValueError):
+        pass
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    threads = min(usable, quota) if quota else usable
+    return threads, {"nproc": os.cpu_count(), "affinity": usable, "cgroup_quota_cpus": quota,
+                     "cpu_model": model}
+
+
 def cpu_baseline(formula, n, P, target_s=12.0):
     """The oracle on a seeded sub-slice: equal-length random k ranges of every
     series, sized from a short probe to take about target_s seconds."""
     import oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads, host = host_cores()
     rows, step = series(formula)
     rng = random.Random(1008)
     d = n - 1
@@ -184,6 +266,7 @@ def cpu_baseline(formula, n, P, target_s=12.0):
     length = int(max(1 << 16, min(1 << 26, target_s / per_term / len(rows))))
     done, dt = run(length)
     return {"value": done / dt, "unit": "terms/s", "cores": threads, "kind": "oracle",
+            "per_core": done / dt / threads, "host": host,
             "sample": "%d series x %d consecutive k at seeded random offsets of the same "
                       "query (%d head terms, %.1f s)" % (len(rows), length, done, dt)}
 
@@ -326,8 +409,34 @@ def integer_only(pb, torch, formula, n, w, P, fast_ms):
         pb.set_arith(pb.ARITH_FAST)
     ms = e0.elapsed_time(e1)
     terms = pb.head_terms(formula, n)
+    headline = (formula, n, w, P) == (pb.BELLARD, 10 ** 12, 256, 320)
+    rf = {"bound": "alu", "peak": PEAK_VALU / 1e12, "unit": "T VALU lane-ops/s"}
+    rf.update(multiply_and_counter_fractions("integer", formula, n, P, terms, ms * 1e-3,
+                                             headline))
+    rf["achieved"] = rf.get("counter_lane_ops_per_s")
+    rf["frac"] = rf.get("issue_frac_counters")
     return {"ms": ms, "terms_per_s": terms / (ms * 1e-3), "fast_over_integer": ms / fast_ms,
+            "dtype": "u32/u64", "roofline": rf,
             "S": "%x" % pb.to_int(out, P), "certified": pb.status_of(st)[0] == pb.PI_OK}
+
+
+def multiply_and_counter_fractions(arith, formula, n, P, terms, seconds, headline):
+    """The int32-multiply roofline of the algorithmic multiply count (a
+    multiply-add per lane per clock: full rate on gfx950, by the probe in
+    profiles/valu_rates.md), and, for the headline query, VALU instructions
+    per term and the issue fraction from the committed SQ_INSTS_VALU count."""
+    mul, mterms = mul32_per_launch(formula, n, P)
+    assert mterms == terms
+    out = {"mul32_per_term": mul / terms, "mul32_frac": mul / seconds / PEAK_VALU,
+           "valu_per_term_counters": None, "issue_frac_counters": None,
+           "counter_lane_ops_per_s": None}
+    c = measured_counters(arith) if headline else None
+    if c:
+        lane_ops = c["sq_insts_valu"] * 64.0
+        out["valu_per_term_counters"] = lane_ops / terms
+        out["counter_lane_ops_per_s"] = lane_ops / seconds / 1e12
+        out["issue_frac_counters"] = lane_ops / seconds / PEAK_VALU
+    return out
 
 
 def other_workloads(pb, torch):
@@ -371,6 +480,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-integer", action="store_true",
                     help="skip timing the query again in integer-only arithmetic")
+    ap.add_argument("--arith", choices=["fast", "integer"], default="fast",
+                    help="arithmetic of the timed steps: exact binary64 where cheaper (the "
+                         "default) or integer Montgomery for every modulus")
     ap.add_argument("--measure-peak", action="store_true",
                     help="run the VALU issue-rate probe and report its rates")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -389,6 +501,8 @@ def main():
     formula = pb.BELLARD if args.formula == "bellard" else pb.BBP
     n, w, P = args.n, args.nbits, args.P
     stream = torch.cuda.current_stream()
+    if args.arith == "integer":
+        pb.set_arith(pb.ARITH_INTEGER)
     if args.copy_probe_mib:
         src = torch.ones(args.copy_probe_mib << 17, dtype=torch.int64, device="cuda")
         dst = torch.empty_like(src)
@@ -419,6 +533,7 @@ def main():
 
     ops, terms = valu_ops_per_launch(formula, n, P)
     assert terms == pb.head_terms(formula, n)
+    headline = (formula, n, w, P) == (pb.BELLARD, 10 ** 12, 256, 320)
     value = terms / (ms * 1e-3)
     achieved = ops / (ms * 1e-3)
     rec = {
@@ -433,7 +548,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u64",
+        "dtype": "u32/u64" if args.arith == "integer" else "binary64-exact+u32/u64",
         "data": "synthetic",
         "config": {"workload": "single query, %s formula, n=%d, %d result bits, P=%d"
                                % (args.formula, n, w, P),
@@ -443,9 +558,18 @@ def main():
         "result_hex": "%0*x" % ((w + 3) // 4, S >> (P - w)),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU / 1e12,
                      "unit": "T VALU lane-ops/s", "frac": achieved / PEAK_VALU,
-                     "traffic": measured_traffic() if (n, w, P, formula) == (10 ** 12, 256, 320, pb.BELLARD) else None,
-                     "valu_ops_per_launch": ops},
+                     "traffic": measured_traffic() if headline and args.arith == "fast" else None,
+                     "valu_ops_per_launch": ops, "valu_per_term_model": ops / terms},
     }
+    rec["roofline"].update(multiply_and_counter_fractions(args.arith, formula, n, P, terms,
+                                                          ms * 1e-3, headline))
+    if args.arith == "integer":
+        # the per-term instruction model describes the default arithmetic only
+        for key in ("achieved", "frac", "valu_ops_per_launch", "valu_per_term_model"):
+            rec["roofline"][key] = None
+        rec["roofline"]["achieved"] = rec["roofline"]["counter_lane_ops_per_s"]
+        rec["roofline"]["frac"] = rec["roofline"]["issue_frac_counters"]
+        rec["arith"] = "integer"
     if n == 10 ** 12 and w == 256 and formula == pb.BELLARD:
         # Table 2.2, m = 12 starts at 10^12 + 1: our bits 1..255
         import re
@@ -453,7 +577,7 @@ def main():
         h = re.search(r"^12 \d+ \d+ ([0-9A-F]+)$", row, re.M).group(1)
         ref = int(h, 16) >> (4 * len(h) - 255)
         rec["matches_table_2_2_m12"] = ((S >> (P - w)) & ((1 << 255) - 1)) == ref
-    if not args.no_integer:
+    if not args.no_integer and args.arith == "fast":
         io = integer_only(pb, torch, formula, n, w, P, ms)
         io["same_bits"] = io.pop("S") == "%x" % S
         rec["integer_only"] = io
