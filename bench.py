@@ -366,7 +366,11 @@ def serving_bench(pb, torch, count=1000, seed=3171, hi_exp=10.0, rho=0.8):
             "steps": st1, "identical_to_burst": res0 == res1,
             "all_certified": all(v[1] == pb.PI_OK for v in res1.values()),
             "workload": "n = floor(10^U), U ~ U(3, %g), BBP/Bellard 1/2 each, w in {64, 256}, "
-                        "P = w + 64, numpy PCG64 seed %d, Poisson arrivals" % (hi_exp, seed)}
+                        "P = w + 64, numpy PCG64 seed %d, Poisson arrivals" % (hi_exp, seed),
+            "scaled": "a %d-query stream of the same recipe with n up to 10^%g, so that the "
+                      "benchmark stays within minutes; the full stream (20,000 queries, n up to "
+                      "10^11, about 25 GPU-minutes) runs as python -m "
+                      "paper_1008_3171_amd.serving burst|stream" % (count, hi_exp)}
 
 
 def paper_slice(pb, torch):
