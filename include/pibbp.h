@@ -67,7 +67,8 @@ enum {
   PI_EINVAL = -1,
   PI_ENOMEM = -2,
   PI_EDEVICE = -3,
-  PI_EUNSUPPORTED = -4
+  PI_EUNSUPPORTED = -4,
+  PI_ESCRATCH = -5
 };
 
 #define PI_MAX_P 1088u
@@ -92,6 +93,21 @@ PI_API int pi_extract(int formula, uint64_t n, uint32_t nbits, uint64_t *out, hi
  *   out: device uint64[ceil(P/64)]. status: device pi_status or NULL. */
 PI_API int pi_extract_ex(int formula, uint64_t n, uint32_t nbits, uint32_t P, uint64_t *out,
                   pi_status *status, hipStream_t stream);
+
+/* pi_extract_ex for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, results and status, bit for bit; the kernels' scratch (the
+ * query's 2*ceil(P/64) carry-save counters and the head launch's chunk
+ * counter, at most 35 64-bit words) is a static device array of 64 words
+ * instead of the library's per-stream arena, so the call allocates nothing
+ * and never waits. Each device holds one such array, shared by every call on
+ * it: calls that overlap on one device (on different streams, or from
+ * different host threads) race and must not be issued; calls on one stream
+ * are ordered and safe. Every call clears what it uses with a kernel (no
+ * hipMemsetAsync). PI_ESCRATCH if a query needed more than the array (not
+ * possible within PI_MAX_P); other errors as pi_extract_ex. */
+PI_API int pi_extract_noalloc(int formula, uint64_t n, uint32_t nbits, uint32_t P, uint64_t *out,
+                              pi_status *status, hipStream_t stream);
 
 /* One summand of eq (3.1), restricted to an index range, as in the
  * partition/compute split of section 4.1: the sum over k in [k0, k1) of

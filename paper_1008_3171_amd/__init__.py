@@ -22,6 +22,7 @@ PI_EINVAL = -1
 PI_ENOMEM = -2
 PI_EDEVICE = -3
 PI_EUNSUPPORTED = -4
+PI_ESCRATCH = -5
 MAX_P = 1088
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -227,6 +228,24 @@ def extract(formula: int, n: int, nbits: int, P: int | None = None, out=None, st
                            ctypes.c_void_p(status.data_ptr()), _stream(stream))
     if rc != 0:
         raise PiError(rc, "pi_extract_ex")
+    return out, status
+
+
+def extract_noalloc(formula: int, n: int, nbits: int, P: int, out, status, stream=None):
+    """pi_extract_noalloc: pi_extract_ex on the library's static device
+    scratch (nothing allocated, nothing waited for). out and status are the
+    caller's; calls that overlap on one device race (see include/pibbp.h)."""
+    lib = load()
+    lib.pi_extract_noalloc.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32,
+                                       ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p]
+    lib.pi_extract_noalloc.restype = ctypes.c_int
+    _check_limbs(out, P)
+    _check_status(status)
+    rc = lib.pi_extract_noalloc(formula, n, nbits, P, ctypes.c_void_p(out.data_ptr()),
+                                ctypes.c_void_p(status.data_ptr()), _stream(stream))
+    if rc != 0:
+        raise PiError(rc, "pi_extract_noalloc")
     return out, status
 
 

@@ -109,7 +109,7 @@ std::atomic<int> g_arith{PI_ARITH_FAST};
 //    residues), then R = 2^62 split at 2^36 so that the small moduli, where a
 //    lane run's start value has the most slack to cover, do not limit the
 //    run length and start bits of the rest.
-void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &out) {
+int head_segments(const QueryPlan &qp, uint32_t acc_off, HeadSeg *out) {
   static const uint64_t kFastLim[7] = {1ull << 22, 1ull << 27, 1ull << 29, 1ull << 33,
                                        1ull << 42, 1ull << 48, 1ull << 51};
   static const uint32_t kFastCls[8] = {22, 27, 29, 33, 42, 48, 51, 64};
@@ -119,6 +119,7 @@ void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &
   const uint64_t *lim = fast ? kFastLim : kIntLim;
   const uint32_t *cls = fast ? kFastCls : kIntCls;
   const int ncls = fast ? 8 : 6;
+  int nseg = 0;
   for (int j = 0; j < kHJ[qp.formula]; ++j) {
     const HostSeries &s = kHSeries[qp.formula][j];
     const uint64_t kb = qp.hk0[j], ke = qp.hk1[j];
@@ -143,9 +144,16 @@ void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &
       g.kb = cuts[c];
       g.ke = cuts[c + 1];
       g.cls = cls[c];
-      out.push_back(g);
+      out[nseg++] = g;
     }
   }
+  return nseg;
+}
+
+void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &out) {
+  HeadSeg segs[kMaxArgSegs];
+  const int n = head_segments(qp, acc_off, segs);
+  out.insert(out.end(), segs, segs + n);
 }
 
 FinQuery fin_query(const QueryPlan &qp, uint64_t out_off, uint32_t status_mode, uint32_t sidx,
@@ -359,10 +367,11 @@ uint32_t safe_pre62(uint32_t run, uint64_t Mmin, uint64_t Mmax, uint64_t a) {
 // allow. Runs held down by those bounds add chunks, so the cap doubles until
 // the query has fewer than 2^31 chunks: its carry-save counters take one
 // value below 2^32 per chunk and stay exact below 2^32 of them.
-uint64_t number_chunks(std::vector<HeadSeg> &segs, uint32_t run_cap, uint64_t chunk_base) {
+uint64_t number_chunks(HeadSeg *segs, size_t nseg, uint32_t run_cap, uint64_t chunk_base) {
   for (;;) {
     uint64_t nchunks = chunk_base;
-    for (HeadSeg &g : segs) {
+    for (size_t i = 0; i < nseg; ++i) {
+      HeadSeg &g = segs[i];
       const HostSeries &s = kHSeries[g.formula][g.j];
       const uint64_t len = g.ke - g.kb;
       uint32_t run = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(run_cap, len / 1024u));
@@ -387,6 +396,10 @@ uint64_t number_chunks(std::vector<HeadSeg> &segs, uint32_t run_cap, uint64_t ch
   }
 }
 
+uint64_t number_chunks(std::vector<HeadSeg> &segs, uint32_t run_cap, uint64_t chunk_base) {
+  return number_chunks(segs.data(), segs.size(), run_cap, chunk_base);
+}
+
 // Smallest run cap that keeps a query below 2^31 chunks (its counters take one
 // value below 2^32 per chunk).
 uint32_t min_run_cap(uint64_t head_terms) {
@@ -394,22 +407,22 @@ uint32_t min_run_cap(uint64_t head_terms) {
 }
 
 // Launch everything for one planned query (head segments passed by value).
+// Its scratch is 2Lk carry-save counters and then the head launch's chunk
+// counter: the library's per-stream arena, or `scratch` when given (at least
+// 2Lk + 1 words, nothing is allocated then).
 int run_single(const QueryPlan &qp, uint64_t *out, pi_status *status, uint32_t mode,
-               hipStream_t st) {
-  std::vector<HeadSeg> segs;
-  head_segments(qp, 0, segs);
-  const int grid_max = resident_grid(qp.Lk, true);
-  const uint64_t nchunks =
-      number_chunks(segs, pick_run(qp.nhead, grid_max, run_cap_for(qp.Lk)), 0);
+               hipStream_t st, unsigned long long *scratch = nullptr) {
   HeadSegTable tab;
   memset(&tab, 0, sizeof tab);
-  for (size_t i = 0; i < segs.size(); ++i) tab.s[i] = segs[i];
-  tab.n = (int)segs.size();
+  tab.n = head_segments(qp, 0, tab.s);
+  const int grid_max = resident_grid(qp.Lk, true);
+  const uint64_t nchunks =
+      number_chunks(tab.s, (size_t)tab.n, pick_run(qp.nhead, grid_max, run_cap_for(qp.Lk)), 0);
   const int Lk = qp.Lk;
   int err = PI_OK;
-  // 2Lk carry-save counters, then the head launch's chunk counter
-  auto *acc =
-      (unsigned long long *)arena(st, (2u * PI_MAX_L + 1u) * sizeof(unsigned long long), &err);
+  auto *acc = scratch ? scratch
+                      : (unsigned long long *)arena(
+                            st, (2u * PI_MAX_L + 1u) * sizeof(unsigned long long), &err);
   if (!acc) return err;
   if (int e = hip_err(launch_zero(acc, 2u * (uint64_t)Lk + 1u, st))) return e;
   if (nchunks) {
@@ -525,6 +538,18 @@ int pi_extract_ex(int formula, uint64_t n, uint32_t nbits, uint32_t P, uint64_t 
   QueryPlan qp;
   if (int e = make_plan(formula, n, nbits, P, 0x7fu, 0, UINT64_MAX, &qp)) return e;
   return run_single(qp, out, status, 1u, stream);
+}
+
+int pi_extract_noalloc(int formula, uint64_t n, uint32_t nbits, uint32_t P, uint64_t *out,
+                       pi_status *status, hipStream_t stream) {
+  if (!out) return PI_EINVAL;
+  QueryPlan qp;
+  if (int e = make_plan(formula, n, nbits, P, 0x7fu, 0, UINT64_MAX, &qp)) return e;
+  unsigned long long *scratch = nullptr;
+  uint32_t words = 0;
+  if (static_scratch(&scratch, &words) != hipSuccess) return PI_EDEVICE;
+  if (2u * (uint32_t)qp.Lk + 1u > words) return PI_ESCRATCH;
+  return run_single(qp, out, status, 1u, stream, scratch);
 }
 
 int pi_extract(int formula, uint64_t n, uint32_t nbits, uint64_t *out, hipStream_t stream) {
@@ -740,6 +765,7 @@ const char *pi_strerror(int code) {
     case PI_ENOMEM: return "out of device memory";
     case PI_EDEVICE: return "HIP runtime or device error";
     case PI_EUNSUPPORTED: return "outside the supported range (modulus >= 2^54 or n too large)";
+    case PI_ESCRATCH: return "needs more than the static scratch of pi_extract_noalloc";
     default: return "unknown error code";
   }
 }

@@ -25,7 +25,11 @@ struct QueryPlan {
 
 int make_plan(int formula, uint64_t n, uint32_t w, uint32_t P, uint32_t jmask, uint64_t k0,
               uint64_t k1, QueryPlan *qp);
+// The head segments of a plan into out[0 .. kMaxArgSegs), returning their count;
+// or appended to a vector.
+int head_segments(const QueryPlan &qp, uint32_t acc_off, HeadSeg *out);
 void head_segments(const QueryPlan &qp, uint32_t acc_off, std::vector<HeadSeg> &out);
+uint64_t number_chunks(HeadSeg *segs, size_t nseg, uint32_t run_cap, uint64_t chunk_base);
 uint64_t number_chunks(std::vector<HeadSeg> &segs, uint32_t run_cap, uint64_t chunk_base);
 uint32_t pick_run(uint64_t head_terms, int grid, uint32_t cap);
 uint32_t run_cap_for(int Lk);

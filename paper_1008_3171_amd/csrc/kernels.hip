@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "arith.h"
 #include "plan.h"
 
@@ -679,6 +681,40 @@ int head_occupancy(int Lk, bool by_value) {
     default: return 0;
   }
 #undef C
+}
+
+// ---- static scratch ---------------------------------------------------------
+
+// The scratch of pi_extract_noalloc, for callers that cannot allocate: one
+// query's 2L carry-save counters and its head launch's chunk counter (at most
+// 2 * 17 + 1 words). Each device holds its own copy until the process ends,
+// and every such call on a device shares it.
+constexpr uint32_t kStaticScratchWords = 64;
+static __device__ __align__(256) unsigned long long scratch[kStaticScratchWords];
+
+// In host code `scratch` names a host-side stand-in, not device memory: its
+// device address comes from the runtime, once per device, with that device
+// current, and only that address is ever passed to a kernel.
+constexpr int kMaxDevices = 64;
+
+hipError_t static_scratch(unsigned long long **ptr, uint32_t *words) {
+  static std::mutex mu;
+  static unsigned long long *addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = (unsigned long long *)p;
+  }
+  *ptr = addr[dev];
+  *words = kStaticScratchWords;
+  return hipSuccess;
 }
 
 hipError_t launch_zero(unsigned long long *p, uint64_t n, hipStream_t st) {

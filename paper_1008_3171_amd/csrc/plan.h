@@ -61,6 +61,9 @@ hipError_t launch_zero(unsigned long long *p, uint64_t n, hipStream_t st);
 // Workgroups of the head kernel instance for Lk limbs that fit on one CU
 // (by_value: the instance taking its segment table as a kernel argument).
 int head_occupancy(int Lk, bool by_value);
+// The device address of the static scratch array on the current device (looked
+// up once per device) and its size in 64-bit words.
+hipError_t static_scratch(unsigned long long **ptr, uint32_t *words);
 hipError_t launch_combine(const uint64_t *parts, int count, int Lq, uint32_t P, uint32_t w,
                           uint64_t nterms, uint32_t J, uint64_t *out, pi_status *status,
                           hipStream_t st);

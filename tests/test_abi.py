@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_strerror():
     lib = pb.load()
-    for code in (0, 1, -1, -2, -3, -4, 99):
+    for code in (0, 1, -1, -2, -3, -4, -5, 99):
         assert lib.pi_strerror(code)
 
 
@@ -60,6 +60,15 @@ def test_invalid_arguments_are_rejected_synchronously():
     assert lib.pi_sum_slice(pb.term_id(0, 4), 10, 0, 5, 64, dummy, null) == E
     assert lib.pi_sum_slice(pb.term_id(1, 0), 10, 6, 5, 64, dummy, null) == E  # k0 > k1
     assert lib.pi_extract(1, 10, 0, dummy, null) == E
+    # the static-scratch variant validates the same way, before any device call
+    lib.pi_extract_noalloc.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32,
+                                       ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p]
+    assert lib.pi_extract_noalloc(2, 10, 8, 72, dummy, null, null) == E
+    assert lib.pi_extract_noalloc(1, 0, 8, 72, dummy, null, null) == E
+    assert lib.pi_extract_noalloc(1, 10, 8, 2000, dummy, null, null) == E
+    assert lib.pi_extract_noalloc(1, 10, 8, 72, null, null, null) == E
+    assert lib.pi_extract_noalloc(1, 2 ** 61, 8, 72, dummy, null, null) == -4
     # moduli from 2^54 up are outside the supported range
     assert lib.pi_extract_ex(1, 2 ** 61, 8, 72, dummy, null, null) == -4
     assert lib.pi_extract_ex(1, 2 ** 55, 8, 72, dummy, null, null) == -4
