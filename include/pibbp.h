@@ -148,9 +148,11 @@ typedef struct {
   uint64_t out_offset;
 } pi_query;
 
-/* Many extractions in one submission: the head terms of every query go
- * through one persistent launch per limb-count class, each query keeps its
- * partial sum on the device, and one finalize launch writes every result.
+/* Many extractions in one submission: the head terms of every query of up
+ * to 6 limbs (P <= 384) go through one persistent launch, whose chunks each
+ * run at their own query's limb count, and those of larger queries through
+ * one launch per limb count (8, 12, 17); each query keeps its partial sum on
+ * the device, and one finalize launch per group writes every result.
  * Each query's result is bit-identical to pi_extract_ex on its own.
  *   q: host array[count]. out: device, packed per out_offset.
  *   status: device pi_status[count] or NULL.
@@ -163,10 +165,14 @@ PI_API int pi_extract_batch(const pi_query *q, int count, uint64_t *out, pi_stat
  * HIP graph and replayed. pi_batch_create plans the queries, allocates the
  * plan's own device memory and uploads its tables (synchronously);
  * pi_batch_launch then only enqueues kernels on `stream` (clear the counters,
- * one head launch per limb class, one finalize launch per class): it never
+ * then per launch group of pi_extract_batch one head and one finalize
+ * launch): it never
  * allocates, copies from the host or waits, so it can be captured. Every
  * launch writes the results again into the out/status given at creation.
- * Launches of one plan must not overlap (they share its counters). */
+ * Launches of one plan must not overlap (they share its counters).
+ * pi_batch_destroy waits for the plan's last eager launch (an event recorded
+ * on its stream, not the whole device) and frees the plan; a plan captured
+ * into a graph must outlive every replay of that graph. */
 typedef struct pi_batch pi_batch;
 PI_API int pi_batch_create(const pi_query *q, int count, uint64_t *out, pi_status *status,
                            pi_batch **plan);
@@ -204,12 +210,16 @@ PI_API int pi_plan_head(int formula, uint32_t series_mask, uint64_t n, uint64_t 
                         uint32_t P, pi_segment *segs, int max_segs, int *count);
 
 /* Launch shape of the head kernel instance for `limbs` = ceil(P/64) rounded
- * up to an instantiated count (1-6, 8, 12, 17), or every instance when limbs
- * is 0: wg_per_cu workgroups per CU (0, the default: as many as fit, from the
- * occupancy API; at most 64) and run_cap, the most indices one lane takes per
- * chunk (1..4096, default 256). Results do not depend on these; only speed
- * does. The autotuner sets them from its cache. PI_EINVAL for limbs outside
- * 0..17 (1..17 for pi_get_tuning), out-of-range values or NULL outputs. */
+ * up to an instantiated count (1-6, 8, 12, 17), of the fused launch that
+ * batches and serving steps use for queries of 1 to 6 limbs when limbs is
+ * PI_TUNE_FUSED, or of every one when limbs is 0: wg_per_cu workgroups per CU
+ * (0, the default: as many as fit, from the occupancy API; at most 64) and
+ * run_cap, the most indices one lane takes per chunk (1..4096, default 256;
+ * for the fused launch, of each query in it). Results do not depend on these; only speed
+ * does. The settings are process-wide (one launch shape per kernel instance
+ * and device). The autotuner sets them from its cache. PI_EINVAL for limbs outside
+ * -1..17 (-1 or 1..17 for pi_get_tuning), out-of-range values or NULL outputs. */
+#define PI_TUNE_FUSED (-1)
 PI_API int pi_set_tuning(int limbs, uint32_t wg_per_cu, uint32_t run_cap);
 PI_API int pi_get_tuning(int limbs, uint32_t *wg_per_cu, uint32_t *run_cap);
 
@@ -222,9 +232,10 @@ PI_API int pi_get_tuning(int limbs, uint32_t *wg_per_cu, uint32_t *run_cap);
  *     same rate as a 32-bit integer multiply-add and needs fewer
  *     instructions); Montgomery below and above;
  *   PI_ARITH_INTEGER: integer Montgomery arithmetic for every modulus.
- * The mode is read when a query is planned (pi_extract*, pi_sum_slice*,
- * pi_extract_batch, pi_batch_create, pi_server_submit). PI_EINVAL for an
- * unknown mode. */
+ * The mode belongs to the calling host thread (each thread starts in
+ * PI_ARITH_FAST) and is read when that thread plans a query (pi_extract*,
+ * pi_sum_slice*, pi_extract_batch, pi_batch_create, pi_server_submit).
+ * PI_EINVAL for an unknown mode. */
 enum { PI_ARITH_FAST = 0, PI_ARITH_INTEGER = 1 };
 PI_API int pi_set_arith(int mode);
 PI_API int pi_get_arith(void);
@@ -238,11 +249,11 @@ PI_API void pi_shutdown(void);
 /* ---- serving: continuous batching ------------------------------------------
  *
  * A server owns a stream-ordered pool of query slots on one device. Queries
- * are admitted while a slot is free (the pool is sized at creation from the
- * device's free memory), each step gives every active query a fair share of
- * the step's head terms, and a query's carry-save partial sum stays in its
- * device slot across steps until its last chunk is done; it is then
- * finalized and its result can be polled. A query's result is bit-identical
+ * are admitted while a slot can be had (the pool grows on demand within a
+ * device-memory cap, see pi_server_set_memory_limit), each step gives every
+ * active query a fair share of the step's head terms, and a query's
+ * carry-save partial sum stays in its device slot across steps until its
+ * last chunk is done; it is then finalized and its result can be polled. A query's result is bit-identical
  * to pi_extract_ex on its own, whatever else is in flight. This is the
  * one-GPU counterpart of section 4.3's admission of small jobs as cluster
  * slots free up. A server is not thread-safe; use one per host thread. */
@@ -261,28 +272,41 @@ typedef struct {
 #define PI_BUSY 2
 
 /* Create a server on the current device and `stream`.
- *   max_active: slots requested (reduced so the pool uses at most a quarter of
- *   the device's free memory); step_terms: head terms per step (the step's
- *   budget, shared fairly by the active queries). */
+ *   max_active: the most queries admitted at once (slots are allocated as
+ *   admission needs them, within the memory cap); step_terms: head terms per
+ *   step (the step's budget, shared fairly by the active queries). */
 PI_API int pi_server_create(uint32_t max_active, uint64_t step_terms, hipStream_t stream,
                             pi_server **out);
 
+/* Cap the device memory the server's query slots may take (bytes; the
+ * default is a quarter of the device memory free at creation). Slots are
+ * allocated on demand, doubling the pool, only while the cap and the
+ * device's free memory (the last eighth is never taken) allow: admission is
+ * by device memory. Lowering the cap below what is in use admits nothing new
+ * until enough queries finish. */
+PI_API int pi_server_set_memory_limit(pi_server *s, size_t bytes);
+
 /* Admit one query (host struct; out_offset is ignored). Returns PI_OK,
- * PI_BUSY when every slot is taken, or an argument error. */
+ * PI_BUSY when no slot can be had (max_active or the memory cap reached), or
+ * an argument error. */
 PI_API int pi_server_submit(pi_server *s, const pi_query *q, uint64_t tag);
 
-/* Run one step on the server's stream and wait for it; *finished (may be
- * NULL) receives the number of queries that completed in it. */
+/* Plan and enqueue one step on the server's stream, then wait for the
+ * previous step (steps are pipelined one deep, so the host plans the next
+ * step while the device runs this one) and deliver its finished queries'
+ * results; with nothing left to plan it waits for every step in flight.
+ * *finished (may be NULL) receives the number of results delivered. */
 PI_API int pi_server_step(pi_server *s, uint32_t *finished);
 
 /* Move up to `max` completed results to `out` (host); *count receives how
  * many. */
 PI_API int pi_server_poll(pi_server *s, pi_result *out, uint32_t max, uint32_t *count);
 
-/* Queries admitted and not yet finished. */
+/* Queries admitted whose results have not been delivered yet. */
 PI_API uint32_t pi_server_active(const pi_server *s);
 
-/* Slots the server was created with (after the memory cap). */
+/* The most queries the server admits at once: max_active, or fewer when
+ * the memory cap allows fewer slots. */
 PI_API uint32_t pi_server_capacity(const pi_server *s);
 
 PI_API void pi_server_destroy(pi_server *s);

@@ -93,14 +93,18 @@ def load():
 
 
 def tuning_cache_path() -> str:
-    """Where the autotuner keeps its choices (PIBBP_TUNING overrides)."""
-    return os.environ.get("PIBBP_TUNING") or os.path.join(
-        os.path.expanduser("~"), ".cache", "pibbp", "tuning.json")
+    """Where the autotuner keeps its choices: tuning.json in this package, as
+    measured on an MI355X and kept with the sources (PIBBP_TUNING names
+    another file; an empty PIBBP_TUNING keeps the library's defaults)."""
+    env = os.environ.get("PIBBP_TUNING")
+    return env if env is not None else os.path.join(_HERE, "tuning.json")
 
 
 def _apply_tuning_cache():
     import json
     path = tuning_cache_path()
+    if not path:
+        return
     try:
         with open(path) as f:
             cache = json.load(f)
@@ -108,6 +112,12 @@ def _apply_tuning_cache():
         return
     for limbs_s, t in cache.get("classes", {}).items():
         _lib.pi_set_tuning(int(limbs_s), int(t["wg_per_cu"]), int(t["run_cap"]))
+    t = cache.get("fused")
+    if t:
+        _lib.pi_set_tuning(-1, int(t["wg_per_cu"]), int(t["run_cap"]))
+
+
+TUNE_FUSED = -1   # pi_set_tuning's key for the fused launch of 1 to 6 limbs
 
 
 def set_tuning(limbs: int, wg_per_cu: int, run_cap: int):
@@ -361,6 +371,8 @@ class Server:
         lib.pi_server_capacity.argtypes = [vp]
         lib.pi_server_capacity.restype = ctypes.c_uint32
         lib.pi_server_destroy.argtypes = [vp]
+        lib.pi_server_set_memory_limit.argtypes = [vp, ctypes.c_size_t]
+        lib.pi_server_set_memory_limit.restype = ctypes.c_int
         for f in (lib.pi_server_create, lib.pi_server_submit, lib.pi_server_step,
                   lib.pi_server_poll):
             f.restype = ctypes.c_int
@@ -375,6 +387,12 @@ class Server:
         self._q = pi_query()
         self._buf = (pi_result * 4096)()
 
+    def set_memory_limit(self, nbytes: int):
+        """pi_server_set_memory_limit: the device bytes its slots may take."""
+        rc = self._lib.pi_server_set_memory_limit(self._h, nbytes)
+        if rc != 0:
+            raise PiError(rc, "pi_server_set_memory_limit")
+
     def submit(self, formula: int, n: int, nbits: int, P: int, tag: int) -> bool:
         """Admit a query; False when every slot is busy."""
         q = self._q
@@ -387,6 +405,8 @@ class Server:
         return True
 
     def step(self) -> int:
+        """Enqueue one step, wait for the previous one; the number of results
+        delivered (poll returns them)."""
         fin = ctypes.c_uint32()
         rc = self._lib.pi_server_step(self._h, ctypes.byref(fin))
         if rc != 0:

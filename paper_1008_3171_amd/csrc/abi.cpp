@@ -10,7 +10,6 @@
 #include <string.h>
 
 #include <algorithm>
-#include <atomic>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -94,8 +93,10 @@ int make_plan(int formula, uint64_t n, uint32_t w, uint32_t P, uint32_t jmask, u
 
 // Arithmetic of the head terms (pi_set_arith): PI_ARITH_FAST uses exact
 // binary64 residues where they are cheapest, PI_ARITH_INTEGER integer
-// Montgomery arithmetic everywhere. Both give the same bits.
-std::atomic<int> g_arith{PI_ARITH_FAST};
+// Montgomery arithmetic everywhere. Both give the same bits. The mode is the
+// calling host thread's own, so one thread's choice never changes how
+// another thread's queries are planned.
+thread_local int g_arith = PI_ARITH_FAST;
 
 // Head segments of a plan, split by modulus range.
 //  * PI_ARITH_FAST: below 2^22 (R = 2^32, Montgomery one by doublings,
@@ -115,7 +116,7 @@ int head_segments(const QueryPlan &qp, uint32_t acc_off, HeadSeg *out) {
   static const uint32_t kFastCls[8] = {22, 27, 29, 33, 42, 48, 51, 64};
   static const uint64_t kIntLim[5] = {1ull << 22, 1ull << 27, 1ull << 29, 1ull << 31, 1ull << 36};
   static const uint32_t kIntCls[6] = {22, 27, 29, 31, 64, 64};
-  const bool fast = g_arith.load() == PI_ARITH_FAST;
+  const bool fast = g_arith == PI_ARITH_FAST;
   const uint64_t *lim = fast ? kFastLim : kIntLim;
   const uint32_t *cls = fast ? kFastCls : kIntCls;
   const int ncls = fast ? 8 : 6;
@@ -276,7 +277,8 @@ void *arena(hipStream_t st, size_t bytes, int *err) {
 
 // Launch shape per kernel limb class: workgroups per CU (0: as many as fit,
 // from the occupancy API) and the cap on indices per lane per chunk. Set by
-// pi_set_tuning (e.g. from the autotuner's cache).
+// pi_set_tuning (e.g. from the autotuner's cache). Entry 0 is the fused launch
+// of queries of 1 to kFusedMaxL limbs (batches, serving steps).
 struct Tuning {
   uint32_t wg_per_cu = 0;
   uint32_t run_cap = 256;
@@ -297,6 +299,34 @@ uint32_t pick_run(uint64_t head_terms, int grid, uint32_t cap) {
 uint32_t run_cap_for(int Lk) {
   std::lock_guard<std::mutex> lk(g_mu);
   return g_tune[Lk].run_cap;
+}
+
+uint32_t run_cap_fused() { return run_cap_for(0); }
+
+// Grid of the fused launch (queries of 1 to kFusedMaxL limbs): CUs x the
+// workgroups per CU its occupancy allows.
+int resident_grid_fused() {
+  const int cus = device_cus();
+  if (cus <= 0) return 2048;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  int occ = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_occ.find({dev, 0});
+    if (it != g_occ.end()) occ = it->second;
+  }
+  if (occ == 0) {
+    occ = std::max(1, head_occupancy_fused());
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_occ[{dev, 0}] = occ;
+  }
+  uint32_t per = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    per = g_tune[0].wg_per_cu;
+  }
+  return cus * (per ? (int)per : occ);
 }
 
 // Grid of a head launch for limb class Lk: CUs x workgroups per CU, from the
@@ -436,14 +466,16 @@ int run_single(const QueryPlan &qp, uint64_t *out, pi_status *status, uint32_t m
 
 // ---- batches -------------------------------------------------------------
 
-// One limb class of a batch: its queries, their head segments and finalize
-// records, and where each lives in the workspace.
+// One launch group of a batch: every query of 1 to kFusedMaxL limbs in the
+// fused kernel (Lk = 0), or the queries of one larger limb class; their head
+// segments and finalize records, and where each lives in the workspace.
 struct ClassPlan {
   int Lk = 0;
   int grid = 2048;  // head launch grid, fixed at planning
   std::vector<HeadSeg> segs;
   std::vector<FinQuery> fins;
   uint64_t nchunks = 0;
+  uint32_t acc_words = 0;  // the queries' carry-save counters, 2 Lk each
   size_t acc_off = 0, seg_off = 0, fin_off = 0;
 };
 struct BatchPlan {
@@ -455,33 +487,36 @@ size_t align256(size_t x) { return (x + 255u) & ~(size_t)255u; }
 
 int plan_batch(const pi_query *q, int count, BatchPlan *bp) {
   if (count < 0 || (count > 0 && !q)) return PI_EINVAL;
-  std::map<int, int> by_class;  // Lk -> index in bp->cls
+  std::map<int, int> by_class;  // launch group (0: fused) -> index in bp->cls
   for (int i = 0; i < count; ++i) {
     if (q[i].reserved != 0) return PI_EINVAL;
     QueryPlan qp;
     if (int e = make_plan(q[i].formula, q[i].n, q[i].nbits, q[i].P, 0x7fu, 0, UINT64_MAX, &qp))
       return e;
-    auto it = by_class.find(qp.Lk);
+    const int group = qp.Lk <= kFusedMaxL ? 0 : qp.Lk;
+    auto it = by_class.find(group);
     if (it == by_class.end()) {
-      it = by_class.emplace(qp.Lk, (int)bp->cls.size()).first;
+      it = by_class.emplace(group, (int)bp->cls.size()).first;
       bp->cls.emplace_back();
-      bp->cls.back().Lk = qp.Lk;
-      bp->cls.back().grid = resident_grid(qp.Lk, false);
+      bp->cls.back().Lk = group;
+      bp->cls.back().grid = group ? resident_grid(group, false) : resident_grid_fused();
     }
     ClassPlan &c = bp->cls[it->second];
-    const uint32_t local = (uint32_t)c.fins.size();
+    const uint32_t local = c.acc_words;
+    c.acc_words += 2u * (uint32_t)qp.Lk;
     std::vector<HeadSeg> segs;
-    head_segments(qp, local * 2u * (uint32_t)qp.Lk, segs);
-    const uint32_t cap = std::max(pick_run(qp.nhead, resident_grid(qp.Lk, false), run_cap_for(qp.Lk)),
-                                  min_run_cap(qp.nhead));
+    head_segments(qp, local, segs);
+    const uint32_t cap = std::max(
+        pick_run(qp.nhead, c.grid, group ? run_cap_for(qp.Lk) : run_cap_fused()),
+        min_run_cap(qp.nhead));
     c.nchunks += number_chunks(segs, cap, c.nchunks);
     c.segs.insert(c.segs.end(), segs.begin(), segs.end());
-    c.fins.push_back(fin_query(qp, q[i].out_offset, 1u, (uint32_t)i, local * 2u * (uint32_t)qp.Lk));
+    c.fins.push_back(fin_query(qp, q[i].out_offset, 1u, (uint32_t)i, local));
   }
   size_t off = 0;
   for (ClassPlan &c : bp->cls) {
     c.acc_off = off;  // carry-save counters of each query, then the chunk counter
-    off = align256(off + (c.fins.size() * 2u * (size_t)c.Lk + 1u) * sizeof(unsigned long long));
+    off = align256(off + ((size_t)c.acc_words + 1u) * sizeof(unsigned long long));
     c.seg_off = off;
     off = align256(off + c.segs.size() * sizeof(HeadSeg));
     c.fin_off = off;
@@ -628,6 +663,8 @@ struct pi_batch {
   char *ws = nullptr;
   uint64_t *out = nullptr;
   pi_status *status = nullptr;
+  hipEvent_t last = nullptr;  // recorded after each launch that is not being captured
+  bool recorded = false;
 };
 
 namespace pibbp {
@@ -640,18 +677,23 @@ int launch_planned(const BatchPlan &bp, char *ws, uint64_t *out, pi_status *stat
     auto *acc = (unsigned long long *)(ws + c.acc_off);
     auto *segs = (HeadSeg *)(ws + c.seg_off);
     auto *fins = (FinQuery *)(ws + c.fin_off);
-    const uint64_t ncount = c.fins.size() * 2u * (uint64_t)c.Lk;
+    const uint64_t ncount = c.acc_words;
     if (int e = hip_err(launch_zero(acc, ncount + 1u, st))) return e;
     if (c.nchunks) {
       const int grid = (int)std::min<uint64_t>(c.nchunks, (uint64_t)grid_max);
-      if (int e = hip_err(launch_head_ptr(c.Lk, segs, (int)c.segs.size(), c.nchunks, grid, acc,
-                                          acc + ncount, st)))
-        return e;
+      const hipError_t he =
+          c.Lk ? launch_head_ptr(c.Lk, segs, (int)c.segs.size(), c.nchunks, grid, acc,
+                                 acc + ncount, st)
+               : launch_head_fused(segs, (int)c.segs.size(), c.nchunks, grid, acc, acc + ncount,
+                                   st);
+      if (int e = hip_err(he)) return e;
     }
     FinQuery none;
     memset(&none, 0, sizeof none);
-    if (int e = hip_err(launch_finalize(c.Lk, none, fins, (int)c.fins.size(), acc, out, status, st)))
-      return e;
+    const hipError_t fe =
+        c.Lk ? launch_finalize(c.Lk, none, fins, (int)c.fins.size(), acc, out, status, st)
+             : launch_finalize_fused(fins, (int)c.fins.size(), acc, out, status, st);
+    if (int e = hip_err(fe)) return e;
   }
   return PI_OK;
 }
@@ -686,6 +728,11 @@ int pi_batch_create(const pi_query *q, int count, uint64_t *out, pi_status *stat
       return PI_EDEVICE;
     }
   }
+  if (hipEventCreateWithFlags(&b->last, hipEventDisableTiming) != hipSuccess) {
+    (void)hipFree(b->ws);
+    delete b;
+    return PI_EDEVICE;
+  }
   b->out = out;
   b->status = status;
   *plan = b;
@@ -694,12 +741,22 @@ int pi_batch_create(const pi_query *q, int count, uint64_t *out, pi_status *stat
 
 int pi_batch_launch(pi_batch *plan, hipStream_t stream) {
   if (!plan) return PI_EINVAL;
-  return launch_planned(plan->bp, plan->ws, plan->out, plan->status, stream);
+  if (int e = launch_planned(plan->bp, plan->ws, plan->out, plan->status, stream)) return e;
+  // an eager launch is marked for pi_batch_destroy; under capture the graph's
+  // replays are the caller's to finish first
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return PI_EDEVICE;
+  if (cs == hipStreamCaptureStatusNone) {
+    if (hipEventRecord(plan->last, stream) != hipSuccess) return PI_EDEVICE;
+    plan->recorded = true;
+  }
+  return PI_OK;
 }
 
 void pi_batch_destroy(pi_batch *plan) {
   if (!plan) return;
-  (void)hipDeviceSynchronize();
+  if (plan->recorded) (void)hipEventSynchronize(plan->last);
+  if (plan->last) (void)hipEventDestroy(plan->last);
   (void)hipFree(plan->ws);
   delete plan;
 }
@@ -729,19 +786,20 @@ int pi_extract_batch(const pi_query *q, int count, uint64_t *out, pi_status *sta
 
 int pi_set_arith(int mode) {
   if (mode != PI_ARITH_FAST && mode != PI_ARITH_INTEGER) return PI_EINVAL;
-  g_arith.store(mode);
+  g_arith = mode;
   return PI_OK;
 }
 
-int pi_get_arith(void) { return g_arith.load(); }
+int pi_get_arith(void) { return g_arith; }
 
 int pi_set_tuning(int limbs, uint32_t wg_per_cu, uint32_t run_cap) {
-  if (limbs < 0 || limbs > PI_MAX_L || run_cap == 0 || run_cap > 4096 || wg_per_cu > 64)
+  if (limbs < PI_TUNE_FUSED || limbs > PI_MAX_L || run_cap == 0 || run_cap > 4096 ||
+      wg_per_cu > 64)
     return PI_EINVAL;
-  const int cls = limbs == 0 ? 0 : limb_class(64u * (uint32_t)limbs);
+  const int cls = limbs <= 0 ? 0 : limb_class(64u * (uint32_t)limbs);
   std::lock_guard<std::mutex> lk(g_mu);
-  for (int L = 1; L <= PI_MAX_L; ++L)
-    if (cls == 0 || L == cls) {
+  for (int L = 0; L <= PI_MAX_L; ++L)
+    if ((limbs == 0) || (limbs == PI_TUNE_FUSED && L == 0) || (limbs > 0 && L == cls)) {
       g_tune[L].wg_per_cu = wg_per_cu;
       g_tune[L].run_cap = run_cap;
     }
@@ -749,8 +807,9 @@ int pi_set_tuning(int limbs, uint32_t wg_per_cu, uint32_t run_cap) {
 }
 
 int pi_get_tuning(int limbs, uint32_t *wg_per_cu, uint32_t *run_cap) {
-  if (limbs < 1 || limbs > PI_MAX_L || !wg_per_cu || !run_cap) return PI_EINVAL;
-  const int cls = limb_class(64u * (uint32_t)limbs);
+  if (limbs < PI_TUNE_FUSED || limbs == 0 || limbs > PI_MAX_L || !wg_per_cu || !run_cap)
+    return PI_EINVAL;
+  const int cls = limbs == PI_TUNE_FUSED ? 0 : limb_class(64u * (uint32_t)limbs);
   std::lock_guard<std::mutex> lk(g_mu);
   *wg_per_cu = g_tune[cls].wg_per_cu;
   *run_cap = g_tune[cls].run_cap;

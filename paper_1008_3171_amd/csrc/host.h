@@ -33,10 +33,12 @@ uint64_t number_chunks(HeadSeg *segs, size_t nseg, uint32_t run_cap, uint64_t ch
 uint64_t number_chunks(std::vector<HeadSeg> &segs, uint32_t run_cap, uint64_t chunk_base);
 uint32_t pick_run(uint64_t head_terms, int grid, uint32_t cap);
 uint32_t run_cap_for(int Lk);
+uint32_t run_cap_fused();
 uint32_t min_run_cap(uint64_t head_terms);
 FinQuery fin_query(const QueryPlan &qp, uint64_t out_off, uint32_t status_mode, uint32_t sidx,
                    uint32_t acc_off);
 int resident_grid(int Lk, bool by_value);
+int resident_grid_fused();
 int hip_err(hipError_t e);
 
 }  // namespace host

@@ -71,19 +71,22 @@ constexpr uint32_t kNoQuery = 0xffffffffu;
 // pending column sums. The lane values are first summed exactly: thread h adds
 // up the 32-bit halves h of all lanes (below 2^40), then thread 0 propagates
 // the carries, so each call adds one value below 2^32 to each pending column.
-// Pending columns belong to one query (counters at acc + pend_off); a chunk of
-// another query first flushes them into that query's carry-save counters with
-// 2L atomics. The counters stay exact while fewer than 2^32 chunks of one
-// query are added up, which the host guarantees.
+// (The 2L threads read one LDS bank at a time; a skewed start per thread
+// would spread them over banks, but costs the head kernel 8 more VGPRs and a
+// workgroup per CU, more than the fold's share of the time.) Pending columns belong to one query (counters at
+// acc + pend_off, *pend_nc of them); a chunk of another query first flushes
+// them into that query's carry-save counters with atomics. The counters stay
+// exact while fewer than 2^32 chunks of one query are added up, which the
+// host guarantees.
 //
 // Thread 0 also claims the workgroup's next chunk from the launch's counter
 // (chunks 0 .. grid-1 are taken first, by block index); the fold's barriers
 // publish it in *next. It is written after the first barrier, so every
 // thread has read the previous value by then.
-template <int L>
+template <int L, int LMAX>
 __device__ __forceinline__ void wg_fold(const uint64_t (&v)[L], uint32_t (*red)[256],
                                         unsigned long long *sums, unsigned long long *pend,
-                                        uint32_t *pend_off, uint32_t acc_off,
+                                        uint32_t *pend_off, uint32_t *pend_nc, uint32_t acc_off,
                                         unsigned long long *acc, unsigned long long *ctr,
                                         unsigned long long *next) {
   const uint32_t tid = threadIdx.x;
@@ -109,25 +112,28 @@ __device__ __forceinline__ void wg_fold(const uint64_t (&v)[L], uint32_t (*red)[
     }
   }
   __syncthreads();
-  if (tid < 2u * L) {
+  if (tid < 2u * LMAX) {
     const uint32_t cur = *pend_off;
     if (cur != acc_off) {
-      if (cur != kNoQuery && pend[tid]) atomicAdd(&acc[(uint64_t)cur + tid], pend[tid]);
+      if (cur != kNoQuery && tid < *pend_nc && pend[tid])
+        atomicAdd(&acc[(uint64_t)cur + tid], pend[tid]);
       pend[tid] = 0;
     }
-    pend[tid] += sums[tid];
+    if (tid < 2u * L) pend[tid] += sums[tid];
   }
   __syncthreads();
-  if (tid == 0) *pend_off = acc_off;
+  if (tid == 0) {
+    *pend_off = acc_off;
+    *pend_nc = 2u * L;
+  }
   __syncthreads();
 }
 
 // The workgroup's last flush of its pending column sums.
-template <int L>
 __device__ __forceinline__ void wg_flush(const unsigned long long *pend, const uint32_t *pend_off,
-                                         unsigned long long *acc) {
+                                         const uint32_t *pend_nc, unsigned long long *acc) {
   const uint32_t tid = threadIdx.x;
-  if (tid < 2u * L && *pend_off != kNoQuery && pend[tid])
+  if (tid < *pend_nc && *pend_off != kNoQuery && pend[tid])
     atomicAdd(&acc[(uint64_t)*pend_off + tid], pend[tid]);
 }
 
@@ -343,64 +349,112 @@ __device__ __forceinline__ void lane_run32(uint64_t k0, uint32_t run, uint64_t k
   }
 }
 
+// The limb count a query of P bits runs at: the smallest instantiated kernel
+// limb class holding P (1-6, 8, 12 or 17 limbs).
+__device__ __forceinline__ int limb_class_of(uint32_t P) {
+  const int Lq = (int)((P + 63u) / 64u);
+  return Lq <= 6 ? Lq : Lq <= 8 ? 8 : Lq <= 12 ? 12 : 17;
+}
+
+// One chunk of one segment at L limbs: every lane sums its run of terms, the
+// sum takes the lanes' common sign, and the workgroup folds the lane sums.
+template <int L, int LMAX>
+__device__ __forceinline__ void head_chunk(const HeadSeg &sg, uint64_t ch, uint32_t (*red)[256],
+                                           unsigned long long *sums, unsigned long long *pend,
+                                           uint32_t *pend_off, uint32_t *pend_nc,
+                                           unsigned long long *acc, unsigned long long *ctr,
+                                           unsigned long long *next) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t pair = tid >> 1, par = tid & 1u;
+  const uint32_t run = sg.run;
+  const uint64_t CH = 256ull * run;
+  const uint64_t kc = sg.kb + (ch - sg.chunk0) * CH;
+  const uint64_t kend = kc + CH < sg.ke ? kc + CH : sg.ke;
+  const DevSeries sr = kSeries[sg.formula][sg.j];
+  const uint64_t step = (uint64_t)kStep[sg.formula];
+  const uint64_t k0 = kc + 2ull * run * pair + par;
+  // every k of this lane has the parity of k0, so one sign for the chunk
+  const bool neg = (sr.neg != 0) ^ (kAlt[sg.formula] != 0 && (k0 & 1u));
+  const uint64_t dc = sg.d + (uint64_t)(int64_t)sr.c;
+  uint64_t sum[L];
+#pragma unroll
+  for (int i = 0; i < L; ++i) sum[i] = 0;
+  switch (sg.cls) {
+    case 64: lane_run62<L>(k0, run, sg.pre, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+    case 51: lane_runf<L, 5, true, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+    case 48: lane_runf<L, 2, false, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+    case 42: lane_runf<L, 3, false, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+    case 33: lane_runf<L, 4, false, 2>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+    case 31: lane_run32<L, 1, true, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+    case 29: lane_run32<L, 1, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+    case 27: lane_run32<L, 2, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+    default: lane_run32<L, 3, false>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+  }
+  if (neg) neg_limbs<L>(sum);
+  wg_fold<L, LMAX>(sum, red, sums, pend, pend_off, pend_nc, sg.acc_off, acc, ctr, next);
+}
+
 // Chunks are handed out dynamically: each workgroup starts at its block
 // index and then takes the next unclaimed chunk from *ctr (zero at launch),
 // so workgroups that draw cheap chunks keep working until the last one.
-template <int L>
+// An instance serves queries of LLO to LHI limbs: one limb count (the single
+// query, and batches of 8, 12 or 17 limbs) or every count from 1 to 6 in one
+// launch (batches and serving steps), each chunk run at its query's count.
+template <int LLO, int LHI>
 __device__ void head_chunks(const HeadSeg *segs, int nseg, uint64_t nchunks,
                             unsigned long long *acc, unsigned long long *ctr) {
-  __shared__ uint32_t red[2 * L][256];
-  __shared__ unsigned long long sums[2 * L], pend[2 * L], next;
-  __shared__ uint32_t pend_off;
+  __shared__ uint32_t red[2 * LHI][256];
+  __shared__ unsigned long long sums[2 * LHI], pend[2 * LHI], next;
+  __shared__ uint32_t pend_off, pend_nc;
   const uint32_t tid = threadIdx.x;
-  const uint32_t pair = tid >> 1, par = tid & 1u;
-  if (tid < 2u * L) pend[tid] = 0;
-  if (tid == 0) pend_off = kNoQuery;
+  if (tid < 2u * LHI) pend[tid] = 0;
+  if (tid == 0) {
+    pend_off = kNoQuery;
+    pend_nc = 0;
+  }
   __syncthreads();
   for (uint64_t ch = blockIdx.x; ch < nchunks; ch = next) {
     const HeadSeg sg = find_seg(segs, nseg, ch);
-    const uint32_t run = sg.run;
-    const uint64_t CH = 256ull * run;
-    const uint64_t kc = sg.kb + (ch - sg.chunk0) * CH;
-    const uint64_t kend = kc + CH < sg.ke ? kc + CH : sg.ke;
-    const DevSeries sr = kSeries[sg.formula][sg.j];
-    const uint64_t step = (uint64_t)kStep[sg.formula];
-    const uint64_t k0 = kc + 2ull * run * pair + par;
-    // every k of this lane has the parity of k0, so one sign for the chunk
-    const bool neg = (sr.neg != 0) ^ (kAlt[sg.formula] != 0 && (k0 & 1u));
-    const uint64_t dc = sg.d + (uint64_t)(int64_t)sr.c;
-    uint64_t sum[L];
-#pragma unroll
-    for (int i = 0; i < L; ++i) sum[i] = 0;
-    switch (sg.cls) {
-      case 64: lane_run62<L>(k0, run, sg.pre, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
-      case 51: lane_runf<L, 5, true, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
-      case 48: lane_runf<L, 2, false, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
-      case 42: lane_runf<L, 3, false, 1>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
-      case 33: lane_runf<L, 4, false, 2>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
-      case 31: lane_run32<L, 1, true, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
-      case 29: lane_run32<L, 1, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
-      case 27: lane_run32<L, 2, true>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
-      default: lane_run32<L, 3, false>(k0, run, kend, sr.a, sr.b, dc, step, sg.P, sum); break;
+#define PIBBP_CHUNK(L) head_chunk<L, LHI>(sg, ch, red, sums, pend, &pend_off, &pend_nc, acc, ctr, &next)
+    if constexpr (LLO == LHI) {
+      PIBBP_CHUNK(LHI);
+    } else {
+      static_assert(LLO == 1 && LHI == 6, "fused instances cover 1 to 6 limbs");
+      switch (limb_class_of(sg.P)) {
+        case 1: PIBBP_CHUNK(1); break;
+        case 2: PIBBP_CHUNK(2); break;
+        case 3: PIBBP_CHUNK(3); break;
+        case 4: PIBBP_CHUNK(4); break;
+        case 5: PIBBP_CHUNK(5); break;
+        default: PIBBP_CHUNK(6); break;
+      }
     }
-    if (neg) neg_limbs<L>(sum);
-    wg_fold<L>(sum, red, sums, pend, &pend_off, sg.acc_off, acc, ctr, &next);
+#undef PIBBP_CHUNK
   }
-  wg_flush<L>(pend, &pend_off, acc);
+  wg_flush(pend, &pend_off, &pend_nc, acc);
 }
 
 template <int L>
 __global__ __launch_bounds__(256) void head_kernel_args(HeadSegTable tab, uint64_t nchunks,
                                                         unsigned long long *acc,
                                                         unsigned long long *ctr) {
-  head_chunks<L>(tab.s, tab.n, nchunks, acc, ctr);
+  head_chunks<L, L>(tab.s, tab.n, nchunks, acc, ctr);
 }
 
 template <int L>
 __global__ __launch_bounds__(256) void head_kernel_ptr(const HeadSeg *segs, int nseg,
                                                        uint64_t nchunks, unsigned long long *acc,
                                                        unsigned long long *ctr) {
-  head_chunks<L>(segs, nseg, nchunks, acc, ctr);
+  head_chunks<L, L>(segs, nseg, nchunks, acc, ctr);
+}
+
+// Every query of 1 to 6 limbs in one persistent launch. Held to 80 VGPRs (six
+// waves per SIMD, as the one-count pointer instances), which it meets without
+// spilling; unbounded it takes 96 and runs five.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void head_kernel_fused(const HeadSeg *segs, int nseg,
+                                                         uint64_t nchunks, unsigned long long *acc,
+                                                         unsigned long long *ctr) {
+  head_chunks<1, 6>(segs, nseg, nchunks, acc, ctr);
 }
 
 __global__ void zero_kernel(unsigned long long *p, uint64_t n) {
@@ -514,15 +568,12 @@ __global__ __launch_bounds__(256) void combine_kernel(const uint64_t *parts, int
   if (status) *status = certify(S, Lq, P, w, nterms, J, 1);
 }
 
-template <int L>
-__global__ __launch_bounds__(256) void finalize_kernel(FinQuery single, const FinQuery *qs,
-                                                       const unsigned long long *acc,
-                                                       uint64_t *out, pi_status *status) {
-  __shared__ uint32_t red[2 * L][256];
-  __shared__ unsigned long long cnt[2 * L];
-  __shared__ unsigned long long nz_total;
+// One query's finalization at L limbs (one workgroup; LDS sized for LMAX).
+template <int L, int LMAX>
+__device__ void finalize_query(const FinQuery &q, const unsigned long long *acc, uint64_t *out,
+                               pi_status *status, uint32_t (*red)[256], unsigned long long *cnt,
+                               unsigned long long &nz_total) {
   const uint32_t tid = threadIdx.x;
-  const FinQuery q = qs ? qs[blockIdx.x] : single;
   const int f = (int)q.formula;
   const int J = kNumSeries[f];
   const int64_t step = kStep[f];
@@ -591,6 +642,35 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinQuery single, const Fi
                                   q.want_status);
 }
 
+template <int L>
+__global__ __launch_bounds__(256) void finalize_kernel(FinQuery single, const FinQuery *qs,
+                                                       const unsigned long long *acc,
+                                                       uint64_t *out, pi_status *status) {
+  __shared__ uint32_t red[2 * L][256];
+  __shared__ unsigned long long cnt[2 * L];
+  __shared__ unsigned long long nz_total;
+  const FinQuery q = qs ? qs[blockIdx.x] : single;
+  finalize_query<L, L>(q, acc, out, status, red, cnt, nz_total);
+}
+
+// Queries of 1 to 6 limbs in one launch, a workgroup each at its own count.
+__global__ __launch_bounds__(256) void finalize_kernel_fused(const FinQuery *qs,
+                                                             const unsigned long long *acc,
+                                                             uint64_t *out, pi_status *status) {
+  __shared__ uint32_t red[12][256];
+  __shared__ unsigned long long cnt[12];
+  __shared__ unsigned long long nz_total;
+  const FinQuery q = qs[blockIdx.x];
+  switch (limb_class_of(q.P)) {
+    case 1: finalize_query<1, 6>(q, acc, out, status, red, cnt, nz_total); break;
+    case 2: finalize_query<2, 6>(q, acc, out, status, red, cnt, nz_total); break;
+    case 3: finalize_query<3, 6>(q, acc, out, status, red, cnt, nz_total); break;
+    case 4: finalize_query<4, 6>(q, acc, out, status, red, cnt, nz_total); break;
+    case 5: finalize_query<5, 6>(q, acc, out, status, red, cnt, nz_total); break;
+    default: finalize_query<6, 6>(q, acc, out, status, red, cnt, nz_total); break;
+  }
+}
+
 // ---- launchers ---------------------------------------------------------------
 
 template <int L>
@@ -614,6 +694,27 @@ static hipError_t launch_fin_L(const FinQuery &single, const FinQuery *qs, int n
                                hipStream_t st) {
   hipLaunchKernelGGL(finalize_kernel<L>, dim3(nq), dim3(256), 0, st, single, qs, acc, out, status);
   return hipGetLastError();
+}
+
+hipError_t launch_head_fused(const HeadSeg *segs, int nseg, uint64_t nchunks, int grid,
+                            unsigned long long *acc, unsigned long long *ctr, hipStream_t st) {
+  hipLaunchKernelGGL(head_kernel_fused, dim3(grid), dim3(256), 0, st, segs, nseg, nchunks, acc,
+                     ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_fused(const FinQuery *qs, int nq, const unsigned long long *acc,
+                                 uint64_t *out, pi_status *status, hipStream_t st) {
+  if (nq <= 0) return hipSuccess;
+  hipLaunchKernelGGL(finalize_kernel_fused, dim3(nq), dim3(256), 0, st, qs, acc, out, status);
+  return hipGetLastError();
+}
+
+int head_occupancy_fused() {
+  int n = 0;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, head_kernel_fused, 256, 0) == hipSuccess
+             ? n
+             : 0;
 }
 
 #define PIBBP_DISPATCH(Lk, CALL)                     \

@@ -58,6 +58,15 @@ hipError_t launch_finalize(int Lk, const FinQuery &single, const FinQuery *qs, i
                            const unsigned long long *acc, uint64_t *out, pi_status *status,
                            hipStream_t st);
 hipError_t launch_zero(unsigned long long *p, uint64_t n, hipStream_t st);
+// Queries of 1 to 6 limbs together: one head launch whose chunks run at their
+// own query's limb count (segments in device memory), and one finalize launch
+// of a workgroup per query.
+constexpr int kFusedMaxL = 6;
+hipError_t launch_head_fused(const HeadSeg *segs, int nseg, uint64_t nchunks, int grid,
+                             unsigned long long *acc, unsigned long long *ctr, hipStream_t st);
+hipError_t launch_finalize_fused(const FinQuery *qs, int nq, const unsigned long long *acc,
+                                 uint64_t *out, pi_status *status, hipStream_t st);
+int head_occupancy_fused();
 // Workgroups of the head kernel instance for Lk limbs that fit on one CU
 // (by_value: the instance taking its segment table as a kernel argument).
 int head_occupancy(int Lk, bool by_value);

@@ -85,6 +85,32 @@ def test_arith_mode_roundtrip_and_limits():
     assert pb.get_arith() == pb.ARITH_FAST
 
 
+def test_arith_mode_belongs_to_the_calling_thread():
+    import threading
+    lib = pb.load()
+    seen = {}
+
+    def other():
+        seen["start"] = lib.pi_get_arith()
+        lib.pi_set_arith(pb.ARITH_INTEGER)
+        seen["set"] = lib.pi_get_arith()
+
+    t = threading.Thread(target=other)
+    t.start()
+    t.join()
+    assert seen == {"start": pb.ARITH_FAST, "set": pb.ARITH_INTEGER}
+    assert pb.get_arith() == pb.ARITH_FAST          # this thread's mode is untouched
+    # and the planner follows the calling thread's mode: class 31 and the
+    # R = 2^62 class from 2^31 exist only in integer mode
+    pb.set_arith(pb.ARITH_INTEGER)
+    try:
+        cls_int = {s["cls"] for s in pb.plan_head(pb.BELLARD, 10 ** 10, 320)}
+    finally:
+        pb.set_arith(pb.ARITH_FAST)
+    cls_fast = {s["cls"] for s in pb.plan_head(pb.BELLARD, 10 ** 10, 320)}
+    assert 31 in cls_int and 31 not in cls_fast
+
+
 def test_tuning_roundtrip_and_limits():
     lib = pb.load()
     before = pb.get_tuning(5)
@@ -99,4 +125,13 @@ def test_tuning_roundtrip_and_limits():
     pb.set_tuning(8, *before8)
     assert lib.pi_set_tuning(5, 0, 0) == -1          # run cap 0
     assert lib.pi_set_tuning(18, 0, 64) == -1        # no such limb count
+    assert lib.pi_set_tuning(-2, 0, 64) == -1
     assert lib.pi_set_tuning(5, 65, 64) == -1
+    # the fused launch of batches and serving steps has a shape of its own
+    before_f = pb.get_tuning(pb.TUNE_FUSED)
+    before5 = pb.get_tuning(5)
+    pb.set_tuning(pb.TUNE_FUSED, 5, 1024)
+    assert pb.get_tuning(pb.TUNE_FUSED) == (5, 1024) and pb.get_tuning(5) == before5
+    pb.set_tuning(pb.TUNE_FUSED, *before_f)
+    a, b = ctypes.c_uint32(), ctypes.c_uint32()
+    assert lib.pi_get_tuning(0, ctypes.byref(a), ctypes.byref(b)) == -1

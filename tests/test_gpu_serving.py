@@ -114,3 +114,56 @@ def test_server_in_a_process_that_loads_the_library_before_torch():
     res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120,
                          cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     assert res.returncode == 0 and "ok" in res.stdout, res.stderr[-2000:]
+
+
+def test_admission_by_device_memory():
+    # the memory cap decides how many queries are admitted at once: find the
+    # cap that allows three slots, fill them, see the fourth refused, and see
+    # it admitted once a slot's query has finished
+    srv = pb.Server(max_active=64, step_terms=1 << 20)
+    srv.set_memory_limit(0)
+    assert srv.capacity() == 0
+    assert not srv.submit(pb.BELLARD, 999, 8, 72, 0)
+    cap_bytes = None
+    for kib in range(1, 1024):
+        srv.set_memory_limit(kib * 1024)
+        if srv.capacity() == 3:
+            cap_bytes = kib * 1024
+            break
+    assert cap_bytes is not None
+    qs = [(pb.BELLARD, 10 ** 6 + i, 64, 128) for i in range(3)] + [(pb.BBP, 4321, 256, 320)]
+    for i, q in enumerate(qs[:3]):
+        assert srv.submit(*q, i)
+    assert not srv.submit(*qs[3], 3)
+    got = {}
+    while srv.active():
+        srv.step()
+        got.update({t: (S, c, N) for t, S, c, N in srv.poll()})
+    assert srv.submit(*qs[3], 3)
+    while srv.active():
+        srv.step()
+        got.update({t: (S, c, N) for t, S, c, N in srv.poll()})
+    srv.close()
+    for i, q in enumerate(qs):
+        assert got[i] == alone(*q), (i, q)
+
+
+def test_slot_pool_grows_on_demand():
+    # more queries at once than the pool's first allocation: it doubles as
+    # admission needs slots, and every result still equals the query alone
+    stream = workloads.serving_stream(300, seed=1008, hi_exp=7.0, rate=1e9)
+    srv = pb.Server(max_active=300, step_terms=1 << 22)
+    assert srv.capacity() == 300
+    for tag, (ta, f, n, w, P) in enumerate(stream):
+        assert srv.submit(f, n, w, P, tag)
+    assert srv.active() == 300
+    got = {}
+    steps = 0
+    while srv.active():
+        srv.step()
+        steps += 1
+        got.update({t: (S, c, N) for t, S, c, N in srv.poll()})
+    srv.close()
+    assert len(got) == 300 and steps > 1
+    for tag, (ta, f, n, w, P) in enumerate(stream):
+        assert got[tag] == alone(f, n, w, P), (tag, f, n, w, P)
