@@ -355,6 +355,10 @@ def serving_bench(pb, torch, count=1000, seed=3171, hi_exp=10.0, rho=0.8):
     capacity = count / mk0
     lam = rho * capacity
     res1, lat1, mk1, st1 = serving.run_stream(srv, base, time_scale=1.0 / lam)
+    # the same stream with unpipelined steps (each step waited for before
+    # the next is planned): lower latency, the device idles while planning
+    srv.set_pipeline(0)
+    res2, lat2, mk2, st2 = serving.run_stream(srv, base, time_scale=1.0 / lam)
     srv.close()
     terms = sum(pb.head_terms(f, n) for _, f, n, _, _ in base)
     print("serving done", file=sys.stderr, flush=True)
@@ -363,7 +367,9 @@ def serving_bench(pb, torch, count=1000, seed=3171, hi_exp=10.0, rho=0.8):
             "makespan_s": mk1, "qps": count / mk1, "terms_per_s": terms / mk1,
             "p50_latency_s": serving.percentile(lat1, 50),
             "p99_latency_s": serving.percentile(lat1, 99),
-            "steps": st1, "identical_to_burst": res0 == res1,
+            "steps": st1, "identical_to_burst": res0 == res1 and res0 == res2,
+            "unpipelined": {"qps": count / mk2, "p50_latency_s": serving.percentile(lat2, 50),
+                            "p99_latency_s": serving.percentile(lat2, 99), "steps": st2},
             "all_certified": all(v[1] == pb.PI_OK for v in res1.values()),
             "workload": "n = floor(10^U), U ~ U(3, %g), BBP/Bellard 1/2 each, w in {64, 256}, "
                         "P = w + 64, numpy PCG64 seed %d, Poisson arrivals" % (hi_exp, seed),

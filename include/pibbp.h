@@ -214,7 +214,7 @@ PI_API int pi_plan_head(int formula, uint32_t series_mask, uint64_t n, uint64_t 
  * batches and serving steps use for queries of 1 to 6 limbs when limbs is
  * PI_TUNE_FUSED, or of every one when limbs is 0: wg_per_cu workgroups per CU
  * (0, the default: as many as fit, from the occupancy API; at most 64) and
- * run_cap, the most indices one lane takes per chunk (1..4096, default 256;
+ * run_cap, the most indices one lane takes per chunk (1..4096, default 2048;
  * for the fused launch, of each query in it). Results do not depend on these; only speed
  * does. The settings are process-wide (one launch shape per kernel instance
  * and device). The autotuner sets them from its cache. PI_EINVAL for limbs outside
@@ -286,16 +286,25 @@ PI_API int pi_server_create(uint32_t max_active, uint64_t step_terms, hipStream_
  * until enough queries finish. */
 PI_API int pi_server_set_memory_limit(pi_server *s, size_t bytes);
 
+/* depth 1 (the default): pi_server_step returns with its step still running
+ * and the host plans the next one meanwhile; a query submitted then joins
+ * the step after next. depth 0: pi_server_step waits for its own step, so a
+ * query submitted after it returns joins the next step, while the device
+ * idles during planning. Higher throughput against lower latency; results
+ * are the same. PI_EINVAL for other depths. */
+PI_API int pi_server_set_pipeline(pi_server *s, int depth);
+
 /* Admit one query (host struct; out_offset is ignored). Returns PI_OK,
  * PI_BUSY when no slot can be had (max_active or the memory cap reached), or
  * an argument error. */
 PI_API int pi_server_submit(pi_server *s, const pi_query *q, uint64_t tag);
 
 /* Plan and enqueue one step on the server's stream, then wait for the
- * previous step (steps are pipelined one deep, so the host plans the next
- * step while the device runs this one) and deliver its finished queries'
- * results; with nothing left to plan it waits for every step in flight.
- * *finished (may be NULL) receives the number of results delivered. */
+ * previous step (pipelined, the default: the host plans the next step while
+ * the device runs this one) or for this one (depth 0), and deliver the
+ * finished queries' results; with nothing left to plan it waits for every
+ * step in flight. *finished (may be NULL) receives the number of results
+ * delivered. */
 PI_API int pi_server_step(pi_server *s, uint32_t *finished);
 
 /* Move up to `max` completed results to `out` (host); *count receives how

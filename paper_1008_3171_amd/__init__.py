@@ -373,6 +373,8 @@ class Server:
         lib.pi_server_destroy.argtypes = [vp]
         lib.pi_server_set_memory_limit.argtypes = [vp, ctypes.c_size_t]
         lib.pi_server_set_memory_limit.restype = ctypes.c_int
+        lib.pi_server_set_pipeline.argtypes = [vp, ctypes.c_int]
+        lib.pi_server_set_pipeline.restype = ctypes.c_int
         for f in (lib.pi_server_create, lib.pi_server_submit, lib.pi_server_step,
                   lib.pi_server_poll):
             f.restype = ctypes.c_int
@@ -393,6 +395,13 @@ class Server:
         if rc != 0:
             raise PiError(rc, "pi_server_set_memory_limit")
 
+    def set_pipeline(self, depth: int):
+        """pi_server_set_pipeline: 1 (default) leaves a step running when step()
+        returns; 0 waits for it."""
+        rc = self._lib.pi_server_set_pipeline(self._h, depth)
+        if rc != 0:
+            raise PiError(rc, "pi_server_set_pipeline")
+
     def submit(self, formula: int, n: int, nbits: int, P: int, tag: int) -> bool:
         """Admit a query; False when every slot is busy."""
         q = self._q
@@ -405,8 +414,8 @@ class Server:
         return True
 
     def step(self) -> int:
-        """Enqueue one step, wait for the previous one; the number of results
-        delivered (poll returns them)."""
+        """Enqueue one step and wait for the previous one (or for this one,
+        unpipelined); the number of results delivered (poll returns them)."""
         fin = ctypes.c_uint32()
         rc = self._lib.pi_server_step(self._h, ctypes.byref(fin))
         if rc != 0:

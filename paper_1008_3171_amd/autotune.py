@@ -33,8 +33,9 @@ SINGLE = {
 SINGLE_WG = (0, 4, 8)
 SINGLE_CAPS = (256, 1024, 2048, 4096)
 FUSED_WG = (0, 4, 5, 8)
-FUSED_CAPS = (64, 256, 1024)
+FUSED_CAPS = (64, 256, 1024, 2048)
 BATCH = dict(count=4096, seed=1008)
+DEFAULT_CAP = 2048        # the library's run cap when nothing is tuned
 
 
 def _timer(torch, stream, fn, reps):
@@ -82,10 +83,10 @@ def batch_runner(pb, torch):
 
 def sweep(pb, key, runner, wgs, caps, log):
     default = pb.get_tuning(key)
-    pb.set_tuning(key, 0, 256)
+    pb.set_tuning(key, 0, DEFAULT_CAP)
     runner()                                       # warm up
     base_ms, ref = runner()
-    best = (base_ms, 0, 256)
+    best = (base_ms, 0, DEFAULT_CAP)
     for wg in wgs:
         for cap in caps:
             pb.set_tuning(key, wg, cap)

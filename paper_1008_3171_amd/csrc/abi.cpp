@@ -281,7 +281,7 @@ void *arena(hipStream_t st, size_t bytes, int *err) {
 // of queries of 1 to kFusedMaxL limbs (batches, serving steps).
 struct Tuning {
   uint32_t wg_per_cu = 0;
-  uint32_t run_cap = 256;
+  uint32_t run_cap = 2048;
 };
 Tuning g_tune[PI_MAX_L + 1];
 std::map<std::pair<int, int>, int> g_occ;  // (device, 2 Lk + by_value) -> workgroups per CU

@@ -10,9 +10,11 @@
 // run; it is then finalized (tail, normalization, certification) and its
 // result is copied to the host.
 //
-// Steps are pipelined one deep: pi_server_step plans and enqueues step N and
-// then waits only for step N-1, so the host plans the next step while the
-// device runs the current one. Everything a step touches that the next one
+// Steps are pipelined one deep by default: pi_server_step plans and enqueues
+// step N and then waits only for step N-1, so the host plans the next step
+// while the device runs the current one (pi_server_set_pipeline(s, 0) waits
+// for step N as well, which lets a query arriving during a step join the very
+// next one, at the cost of the device idling while the host plans). Everything a step touches that the next one
 // could overwrite (tables, result rows, host staging, chunk counters) is
 // double-buffered by step parity; the carry-save slots are ordered by the
 // stream alone.
@@ -95,6 +97,7 @@ struct pi_server {
   unsigned long long *acc = nullptr;  // cap x kSlotCounters, then 2 x kChunkCounters
   StepBuf buf[2];
   int parity = 0;
+  int depth = 1;                      // steps left running when pi_server_step returns
   uint32_t in_flight = 0;             // finished queries not yet harvested
   std::vector<uint32_t> free_slots;
   std::vector<Active> active;
@@ -412,9 +415,18 @@ int pi_server_step(pi_server *s, uint32_t *finished) {
     }
   s->active.resize(w);
   s->parity ^= 1;
-  // 7. wait for the previous step (this one runs on) and deliver its results
+  // 7. wait for the previous step (this one runs on) and deliver its results;
+  //    unpipelined, wait for this one too
   if (int e = harvest(s, prev, true)) return e;
+  if (s->depth == 0)
+    if (int e = harvest(s, b, true)) return e;
   if (finished) *finished = (uint32_t)(s->done.size() - before);
+  return PI_OK;
+}
+
+int pi_server_set_pipeline(pi_server *s, int depth) {
+  if (!s || depth < 0 || depth > 1) return PI_EINVAL;
+  s->depth = depth;
   return PI_OK;
 }
 

@@ -36,6 +36,21 @@ def test_results_alone_equal_results_in_the_mix():
         assert results[tag] == (S, 0 if cert else 1, N)
 
 
+def test_unpipelined_steps_give_the_same_results():
+    stream = workloads.serving_stream(120, seed=77, hi_exp=7.0, rate=2000.0)
+    out = []
+    for depth in (1, 0):
+        srv = pb.Server(max_active=24, step_terms=1 << 21)
+        srv.set_pipeline(depth)
+        results, lat, makespan, steps = serving.run_stream(srv, stream)
+        srv.close()
+        assert len(results) == len(stream) and steps > 5
+        out.append(results)
+    assert out[0] == out[1]
+    with pytest.raises(pb.PiError):
+        pb.Server(max_active=2).set_pipeline(2)
+
+
 def test_admission_busy_and_slot_reuse():
     srv = pb.Server(max_active=2, step_terms=1 << 20)
     assert srv.capacity() == 2
