@@ -39,6 +39,7 @@ namespace {
 constexpr uint32_t kSlotCounters = 2u * PI_MAX_L;  // carry-save counters per slot
 constexpr uint32_t kChunkCounters = 16;             // one per head launch of a step (<= 9)
 constexpr uint32_t kFirstSlots = 64;                // slots allocated at creation (at most)
+constexpr uint64_t kStepChunksPerSlot = 8;          // chunks per workgroup slot in a full step
 
 // Device bytes one admitted query can need: its counters, a result row and
 // status, and its share of a step's tables (up to kMaxArgSegs segments and
@@ -263,11 +264,16 @@ int pi_server_submit(pi_server *s, const pi_query *q, uint64_t tag) {
   s->free_slots.pop_back();
   a.tag = tag;
   head_segments(a.qp, a.slot * kSlotCounters, a.segs);
+  // A step covers at most step_terms head terms across all queries, so its
+  // chunks are kept small enough that every workgroup slot of the launch gets
+  // several of them (kStepChunksPerSlot); a long run fits a whole-query launch
+  // but leaves a step with a few huge chunks and an idle tail.
   const bool fused = a.qp.Lk <= kFusedMaxL;
   const int grid = fused ? resident_grid_fused() : resident_grid(a.qp.Lk, false);
-  const uint32_t cap =
-      std::max(pick_run(a.qp.nhead, grid, fused ? run_cap_fused() : run_cap_for(a.qp.Lk)),
-               min_run_cap(a.qp.nhead));
+  const uint64_t step_run = s->step_terms / (256ull * (uint64_t)grid * kStepChunksPerSlot);
+  const uint32_t tuned = fused ? run_cap_fused() : run_cap_for(a.qp.Lk);
+  const uint32_t run_cap = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(tuned, step_run));
+  const uint32_t cap = std::max(pick_run(a.qp.nhead, grid, run_cap), min_run_cap(a.qp.nhead));
   a.nchunks = number_chunks(a.segs, cap, 0);
   s->active.push_back(std::move(a));
   return PI_OK;
