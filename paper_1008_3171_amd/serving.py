@@ -9,12 +9,15 @@ Command line (the seeded serving stream; two phases so that each fits one
 run of a few minutes):
 
     python -m paper_1008_3171_amd.serving burst  --count 20000 --out burst.json
-    python -m paper_1008_3171_amd.serving stream --count 20000 --burst burst.json
+    python -m paper_1008_3171_amd.serving stream --count 20000 --burst burst.json --record rec.json
 
 `burst` submits every query at once and reports capacity (queries/s) and the
 results; `stream` replays the same queries as Poisson arrivals at rho times
 that capacity, reports p50/p99 latency and checks every result against the
-burst's.
+burst's. `--record` also writes the stream's summary, a SHA-256 over all its
+results, and the results of every query with n <= 10^5 plus a seeded sample
+of 300 with 10^5 < n <= 10^7, small enough to check against an independent
+CPU evaluation.
 """
 from __future__ import annotations
 
@@ -64,6 +67,31 @@ def run_stream(server, stream, time_scale: float = 1.0, progress=None):
     return results, lat, makespan, steps
 
 
+def results_digest(queries, results) -> str:
+    """SHA-256 over every (tag, formula, n, nbits, P, S, code, N), in tag order."""
+    import hashlib
+    h = hashlib.sha256()
+    for tag in sorted(results):
+        ta, f, n, w, P = queries[tag]
+        S, code, N = results[tag]
+        h.update(("%d %d %d %d %d %x %d %d\n" % (tag, f, n, w, P, S, code, N)).encode())
+    return h.hexdigest()
+
+
+def write_record(path, summary, queries, results, burst):
+    import random
+    small = [t for t in sorted(results) if queries[t][2] <= 10 ** 5]
+    mid = [t for t in sorted(results) if 10 ** 5 < queries[t][2] <= 10 ** 7]
+    pick = sorted(small + random.Random(3171).sample(mid, min(300, len(mid))))
+    rec = dict(summary)
+    rec["burst"] = {k: burst[k] for k in ("makespan_s", "capacity_qps", "terms_per_s", "steps")}
+    rec["results_sha256"] = results_digest(queries, results)
+    rec["checked_results"] = [[t, queries[t][1], queries[t][2], queries[t][3], queries[t][4],
+                               "%x" % results[t][0], results[t][1], results[t][2]] for t in pick]
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=0)
+
+
 def percentile(xs, p):
     if not xs:
         return float("nan")
@@ -87,6 +115,7 @@ def main(argv=None) -> int:
     ap.add_argument("--out", help="burst: where to write capacity and results")
     ap.add_argument("--burst", help="stream: the burst phase's output file")
     ap.add_argument("--step-terms", type=int, default=1 << 30)
+    ap.add_argument("--record", help="stream: where to write the summary and checkable results")
     args = ap.parse_args(argv)
 
     import paper_1008_3171_amd as pb
@@ -120,6 +149,8 @@ def main(argv=None) -> int:
                     "p50_latency_s": percentile(lat, 50), "p99_latency_s": percentile(lat, 99),
                     "identical_to_burst": same and len(res) == len(burst["results"]),
                     "all_certified": all(v[1] == pb.PI_OK for v in res.values())})
+        if args.record:
+            write_record(args.record, rec, base, res, burst)
     srv.close()
     print(json.dumps(rec), flush=True)
     return 0
