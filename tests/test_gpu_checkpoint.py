@@ -59,19 +59,21 @@ def test_combine_certifies_like_extract():
 
 @pytest.mark.timeout(600)
 def test_table_2_2_row_m13_checkpointed(tmp_path):
-    # n = 10^13 + 1: 7.0e12 head terms, about 63 s on one MI355X, in 28
-    # checkpointed pieces; the 256 bits must equal the printed row, certified
+    # n = 10^13 + 1: 7.0e12 head terms, about 71 s on one MI355X at P = 1088, in
+    # 28 checkpointed pieces; every printed bit (1000) must equal the row,
+    # certified, with N equal to its definition
     row = [r for r in read_golden("table_2_2.txt") if r[0] == "13"][0]
-    n = int(row[1])
-    ck = checkpoint.plan(pb.BELLARD, n, 256, 320, 4)
+    n, nbits = int(row[1]), int(row[2])
+    P = 1088
+    ck = checkpoint.plan(pb.BELLARD, n, nbits, P, 4)
     path = str(tmp_path / "m13.json")
     checkpoint.save(ck, path)
     checkpoint.run(checkpoint.load(path), path, 1e9, log=sys.stdout)
     ck = checkpoint.load(path)
     S, code, N = checkpoint.finish(ck)
-    assert N == n_definition(pb.BELLARD, n - 1, 320)
+    assert N == n_definition(pb.BELLARD, n - 1, P)
     assert code == pb.PI_OK
-    assert S >> 64 == hex_bits(row[3], 256)
+    assert S >> (P - nbits) == hex_bits(row[3], nbits)
 
 
 def test_double_run_overlap():
