@@ -182,3 +182,29 @@ def test_slot_pool_grows_on_demand():
     assert len(got) == 300 and steps > 1
     for tag, (ta, f, n, w, P) in enumerate(stream):
         assert got[tag] == alone(f, n, w, P), (tag, f, n, w, P)
+
+
+def test_steps_mixing_fused_and_wide_queries():
+    # queries of 1 to 6 limbs share a step's fused launch; wider ones (8, 12,
+    # 17 limbs) get their own launches in the same step; every result equals
+    # the query alone
+    rng = random.Random(4242)
+    qs = []
+    for i in range(36):
+        P = rng.choice([64, 96, 192, 320, 384, 448, 640, 1024, 1088])
+        qs.append((rng.choice([pb.BBP, pb.BELLARD]), rng.randrange(1, 3_000_000),
+                   rng.randrange(1, P + 1), P))
+    for depth in (1, 0):
+        srv = pb.Server(max_active=12, step_terms=1 << 20)
+        srv.set_pipeline(depth)
+        got, i, steps = {}, 0, 0
+        while i < len(qs) or srv.active():
+            while i < len(qs) and srv.submit(*qs[i], i):
+                i += 1
+            srv.step()
+            steps += 1
+            got.update({t: (S, c, N) for t, S, c, N in srv.poll()})
+        srv.close()
+        assert steps > 3 and len(got) == len(qs)
+        for t, q in enumerate(qs):
+            assert got[t] == alone(*q), (depth, t, q)
