@@ -42,9 +42,28 @@ def plan(formula: int, n: int, nbits: int, P: int, pieces: int) -> dict:
     return {"formula": formula, "n": n, "nbits": nbits, "P": P, "items": items}
 
 
+def validate(ck: dict) -> None:
+    """Every series of the formula must have pieces that tile its index range
+    [0, (n + P) // step + 2) exactly once: a piece dropped, duplicated or
+    overlapping would silently change the sum, so it raises ValueError."""
+    f = ck["formula"]
+    kmax = (ck["n"] + ck["P"]) // STEP[f] + 2
+    for j in range(NSERIES[f]):
+        rs = sorted((it["k0"], it["k1"]) for it in ck["items"] if it["j"] == j)
+        if not rs or rs[0][0] != 0 or rs[-1][1] != kmax:
+            raise ValueError("series %d does not cover [0, %d)" % (j, kmax))
+        for a, b in zip(rs, rs[1:]):
+            if a[1] != b[0]:
+                raise ValueError("series %d: pieces [%d, %d) and [%d, %d) leave a gap or overlap"
+                                 % (j, a[0], a[1], b[0], b[1]))
+    if any(not 0 <= it["j"] < NSERIES[f] for it in ck["items"]):
+        raise ValueError("a piece names a series the formula does not have")
+
+
 def load(path: str) -> dict:
     with open(path) as f:
         ck = json.load(f)
+    validate(ck)
     for it in ck["items"]:
         if it["S"] is not None and it["hash"] != _digest(it):
             it["S"] = it["N"] = it["hash"] = None          # damaged: compute again

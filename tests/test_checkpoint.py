@@ -1,6 +1,9 @@
 """Checkpoint bookkeeping (CPU): the pieces partition every series' index
 range exactly, the file round-trips, and a damaged piece is recomputed."""
+import copy
 import json
+
+import pytest
 
 from paper_1008_3171_amd import checkpoint
 
@@ -29,3 +32,26 @@ def test_roundtrip_and_damaged_piece_is_recomputed(tmp_path):
     json.dump(raw, open(path, "w"))
     back = checkpoint.load(path)
     assert 3 in checkpoint.pending(back)
+
+
+def test_dropped_duplicated_or_overlapping_pieces_fail_loudly(tmp_path):
+    path = str(tmp_path / "ck.json")
+    ck = checkpoint.plan(1, 10 ** 7 + 1, 256, 320, 4)
+    checkpoint.validate(ck)
+    bad = []
+    dropped = copy.deepcopy(ck)
+    del dropped["items"][5]
+    bad.append(dropped)
+    duplicated = copy.deepcopy(ck)
+    duplicated["items"].append(copy.deepcopy(ck["items"][9]))
+    bad.append(duplicated)
+    overlapping = copy.deepcopy(ck)
+    overlapping["items"][2]["k1"] += 1
+    bad.append(overlapping)
+    foreign = copy.deepcopy(ck)
+    foreign["items"].append(dict(ck["items"][0], j=7))
+    bad.append(foreign)
+    for b in bad:
+        checkpoint.save(b, path)
+        with pytest.raises(ValueError):
+            checkpoint.load(path)
