@@ -135,3 +135,40 @@ def test_tuning_roundtrip_and_limits():
     pb.set_tuning(pb.TUNE_FUSED, *before_f)
     a, b = ctypes.c_uint32(), ctypes.c_uint32()
     assert lib.pi_get_tuning(0, ctypes.byref(a), ctypes.byref(b)) == -1
+
+
+def test_binding_fails_loudly_without_a_gpu():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(RuntimeError, match="no GPU"):
+        pb.extract(pb.BELLARD, 1000, 256)
+
+
+def test_binding_refuses_host_buffers_before_the_library(monkeypatch):
+    # every wrapper that takes a caller's buffer checks it first: host tensors
+    # never reach the kernels. Nothing here reaches the library, so the test
+    # runs without a GPU once the binding's device check is told there is one.
+    torch = pytest.importorskip("torch")
+    monkeypatch.setattr(torch.cuda, "is_available", lambda: True)
+    P = 320
+    host = torch.zeros(pb.limbs(P), dtype=torch.int64)
+    hst = torch.zeros(4, dtype=torch.int32)
+    with pytest.raises(ValueError, match="GPU"):
+        pb.extract(pb.BELLARD, 1000, 256, P, out=host, status=hst)
+    with pytest.raises(ValueError, match="GPU"):
+        pb.extract_noalloc(pb.BELLARD, 1000, 256, P, host, hst)
+    with pytest.raises(ValueError, match="GPU"):
+        pb.extract_default(pb.BELLARD, 1000, 256, out=host)
+    with pytest.raises(ValueError, match="GPU"):
+        pb.sum_slice(pb.term_id(pb.BELLARD, 0), 1000, 0, 10, P, out=host)
+    with pytest.raises(ValueError, match="GPU"):
+        pb.combine(torch.zeros(2 * pb.limbs(P), dtype=torch.int64), 2, P, 256, 7, 100,
+                   out=host, status=hst)
+    qarr, total = pb.make_queries([(pb.BELLARD, 1000, 64, 128), (pb.BBP, 2000, 256, 320)])
+    with pytest.raises(ValueError, match="GPU"):
+        pb.extract_batch(qarr, 2, torch.zeros(total, dtype=torch.int64), status=False)
+    with pytest.raises(ValueError, match="GPU"):
+        pb.BatchPlan(qarr, 2, torch.zeros(total, dtype=torch.int64))
+    with pytest.raises(ValueError, match="outside"):
+        pb.extract_batch(qarr, 3, host, status=False)
