@@ -16,11 +16,15 @@ G + B <= 2^g, B = N + 2J units of 2^-P). These tests check
 * N (every head index plus every tail index before the first zero
   truncation) against its definition, counted in Python integers;
 * and that a mistake planted in a copy of the oracle's C (one side of the
-  test dropped, the stop index counted, an index lost) fails these pins.
+  test dropped, the stop index counted, an index lost) fails these pins, and
+  that a mistake planted in its arithmetic (a sign, a power, an exponent, a
+  transposed operand, a shift, a reordered ladder) fails the arithmetic pins
+  of the other test file, run here on the planted copy.
 """
 import os
 import random
 from concurrent.futures import ThreadPoolExecutor
+from fractions import Fraction
 
 import pytest
 
@@ -275,3 +279,120 @@ def test_planted_mistake_fails_a_pin(name, tmp_path, machin):
 def test_unchanged_copy_passes_the_same_pins(tmp_path, machin):
     # the copy-and-build route itself changes nothing
     assert pins_pass(planted(tmp_path, "return ge && le;", "return ge && le;"), machin)
+
+
+# ---- planted arithmetic mistakes fail the arithmetic pins -------------------
+
+ARITH_MISTAKES = {
+    "a wrong sign in one of Bellard's series": ("{-1, -4, 10, 5}", "{+1, -4, 10, 5}"),
+    "a BBP denominator not halved (wrong power of two)": ("{-1, -1, 2, 1}", "{-1, 0, 2, 1}"),
+    "the alternating sign dropped": (
+        "int neg = (jb->sr.sign < 0) ^ (jb->alt < 0 && (k & 1u));",
+        "int neg = (jb->sr.sign < 0);"),
+    "a term's exponent off by one": (
+        "  int64_t E = (int64_t)d + sr->c - (int64_t)step * (int64_t)k;\n  uint64_t M",
+        "  int64_t E = (int64_t)d + sr->c - (int64_t)step * (int64_t)k + 1;\n  uint64_t M"),
+    "the modulus's operands transposed (b k + a)": (
+        "uint64_t M = sr->a * k + sr->b;", "uint64_t M = sr->b * k + sr->a;"),
+    "a tail term's precision off by one": (
+        "int64_t bits = (int64_t)P + E;", "int64_t bits = (int64_t)P + E - 1;"),
+    "the quotient's final shift off by one": (
+        "uint32_t s = 32u * nd - bits;", "uint32_t s = 32u * nd - bits + 1u;"),
+    "the ladder squares before it multiplies": (
+        "    if (e & 1u) result = (uint64_t)((u128)result * base % m);\n"
+        "    base = (uint64_t)((u128)base * base % m);",
+        "    base = (uint64_t)((u128)base * base % m);\n"
+        "    if (e & 1u) result = (uint64_t)((u128)result * base % m);"),
+}
+
+
+def printed_formula(formula, kmax):
+    """eq (1.1) or (1.2) as printed, summed to kmax in exact rationals."""
+    F = Fraction
+    tot = F(0)
+    for k in range(kmax):
+        if formula == oracle.BBP:
+            tot += F(1, 16 ** k) * (F(4, 8 * k + 1) - F(2, 8 * k + 4) - F(1, 8 * k + 5)
+                                    - F(1, 8 * k + 6))
+        else:
+            tot += F((-1) ** k, 2 ** (10 * k)) * (
+                F(4, 10 * k + 1) - F(1, 10 * k + 3) - F(1, 16 * (10 * k + 5))
+                - F(1, 16 * (10 * k + 7)) + F(1, 64 * (10 * k + 9))
+                - F(1, 2 * (4 * k + 1)) - F(1, 64 * (4 * k + 3)))
+    return tot
+
+
+# The series of the printed formulas in the form sign 2^c / (a k + b), written
+# out here (not read from the oracle) and pinned to the printed formulas below.
+WRITTEN = {
+    oracle.BBP: (4, +1, [(+1, 2, 8, 1), (-1, -1, 2, 1), (-1, 0, 8, 5), (-1, -1, 4, 3)]),
+    oracle.BELLARD: (10, -1, [(+1, 2, 10, 1), (-1, 0, 10, 3), (-1, -4, 10, 5), (-1, -4, 10, 7),
+                              (+1, -6, 10, 9), (-1, -1, 4, 1), (-1, -6, 4, 3)]),
+}
+
+
+def exact_term_printed(formula, j, d, k, P):
+    """floor(2^P frac(2^E / M)) from exact rationals, with the series of
+    WRITTEN."""
+    step, _, rows = WRITTEN[formula]
+    _, c, a, b = rows[j]
+    E, M = d + c - step * k, a * k + b
+    x = Fraction(2 ** E, M) if E >= 0 else Fraction(1, 2 ** (-E) * M)
+    v = (x - x.numerator // x.denominator) * 2 ** P
+    return v.numerator // v.denominator
+
+
+def arith_pins_pass(orc, machin):
+    """The arithmetic pins of the other oracle test file, on another copy of
+    the oracle: the tables sum to the printed formulas, the modular power
+    equals Python's, terms equal exact rationals, and certified windows hold
+    Machin's bits. False at the first failure."""
+    try:
+        for f, kmax in ((oracle.BBP, 40), (oracle.BELLARD, 20)):
+            rows, step, alt = orc.series_table(f)
+            tot = sum(sign * alt ** k * Fraction(2) ** (c - step * k) / (a * k + b)
+                      for k in range(kmax) for sign, c, a, b in rows)
+            assert tot == printed_formula(f, kmax)
+        rng = random.Random(77)
+        for _ in range(300):
+            m = rng.randrange(1, 2 ** rng.randrange(1, 63))
+            e = rng.randrange(0, 2 ** 62)
+            assert orc.pow2mod(e, m) == pow(2, e, m)
+        for f in FORMULAS:
+            J = 4 if f == oracle.BBP else 7
+            step = 4 if f == oracle.BBP else 10
+            for _ in range(200):
+                d = rng.randrange(0, 200)
+                j = rng.randrange(J)
+                k = rng.randrange(0, d // step + 30)
+                P = rng.choice([1, 7, 31, 32, 33, 63, 64, 65, 96, 128, 200])
+                assert orc.term(f, j, d, k, P) == exact_term_printed(f, j, d, k, P)
+        certified = 0
+        for f in FORMULAS:
+            for n in range(1, 301):
+                S, N, cert = orc.extract(f, n, 16, 48)
+                if cert:
+                    certified += 1
+                    assert S >> 32 == machin_window(machin, n, 16)
+        assert certified > 550
+    except AssertionError:
+        return False
+    return True
+
+
+def test_written_out_series_are_the_printed_formulas():
+    for f, kmax in ((oracle.BBP, 30), (oracle.BELLARD, 15)):
+        step, alt, rows = WRITTEN[f]
+        tot = sum(sign * alt ** k * Fraction(2) ** (c - step * k) / (a * k + b)
+                  for k in range(kmax) for sign, c, a, b in rows)
+        assert tot == printed_formula(f, kmax)
+
+
+@pytest.mark.parametrize("name", sorted(ARITH_MISTAKES))
+def test_planted_arithmetic_mistake_fails_a_pin(name, tmp_path, machin):
+    old, new = ARITH_MISTAKES[name]
+    assert not arith_pins_pass(planted(tmp_path, old, new), machin), name
+
+
+def test_unchanged_copy_passes_the_arithmetic_pins(tmp_path, machin):
+    assert arith_pins_pass(planted(tmp_path, "return ge && le;", "return ge && le;"), machin)
