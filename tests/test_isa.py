@@ -9,7 +9,9 @@ checked for what the design relies on:
   round, an add) in every window loop of the ladder: 2-, 3- and 4-bit windows
   add the digit's extraction and ldexp, five-bit windows add their separate
   digit step (multiply, round, FMA and the extraction and ldexp);
-* a step on 31-bit digits (R = 2^62) is nine 32-bit multiplies.
+* a step on 31-bit digits (R = 2^62) is nine 32-bit multiplies;
+* bench.py's per-term instruction model prices every modulus class's window
+  and the carry step as they were compiled.
 """
 import collections
 import shutil
@@ -89,3 +91,26 @@ def test_montgomery_step_on_31_bit_digits_is_nine_multiplies(asm):
         muls = [c["v_mad_u64_u32"] + c["v_mul_lo_u32"] for c in loops_of(asm, kernel)
                 if c["v_mad_u64_u32"] >= 7]
         assert muls and all(m == 9 for m in muls), (kernel, muls)
+
+
+def test_per_term_model_matches_the_compiled_window_loops(asm):
+    # bench.py prices each modulus class at (window bits W) x (per squaring)
+    # + (per window) instructions per whole window; the compiled head kernel
+    # has a window loop of exactly that many VALU instructions for each class
+    # (class 62 steps one bit at a time; one copy of its loop keeps one more
+    # mask). The carry step over the digit sums is 28 at 5 limbs.
+    import bench
+    counts = {}
+    for c in loops_of(asm, "head_kernel_args<5>"):
+        v = sum(valu(c).values())
+        counts[v] = counts.get(v, 0) + 1
+    for name, _, W, per_sq, per_win, _, _ in bench.KERNEL_CLASSES:
+        want = W * per_sq + per_win
+        assert counts.get(want, 0) >= 1, (name, want, counts)
+    assert counts.get(16) and counts.get(17)
+    assert round(bench.FP_EXTRA_PER_TERM * 120 - 81 * 120 / 256) == 28
+    carry = [c for c in loops_of(asm, "head_kernel_args<5>")
+             if valu(c) == collections.Counter({"v_ldexp_f64": 7, "v_floor_f64_e32": 7,
+                                                "v_fmac_f64_e32": 7, "v_add_f64": 7,
+                                                "v_mov_b64_e32": 1})]
+    assert len(carry) == 4                         # one per binary64 class
