@@ -6,8 +6,9 @@ a partition of the index range [0, (n + P) // step + 2) (every head index and
 every nonzero tail index) into `pieces` ranges. `run` computes pending pieces
 with pi_sum_slice_ex, one at a time, and rewrites the file after each; a
 piece stores its partial sum S, its index count N and a hash of both, and a
-piece whose hash does not match is computed again. `finish` adds the partial
-sums on the device with pi_combine and certifies the total.
+piece whose hash does not match is computed again, and a file whose pieces do
+not tile every series' range exactly once is refused. `finish` adds the
+partial sums on the device with pi_combine and certifies the total.
 
     python -m paper_1008_3171_amd.checkpoint plan  FILE --formula bellard --n N --nbits W --P P --pieces K
     python -m paper_1008_3171_amd.checkpoint run   FILE --budget SECONDS
