@@ -64,17 +64,47 @@ def test_finished_pieces_count_their_indices(record):
         assert it["N"] == want, it
 
 
+def combine_on_cpu(ck):
+    """(S, N, certified) of a complete record: the pieces' left-aligned L-limb
+    partial sums added mod 2^(64L), shifted down to P bits, and certified
+    against B = N + 2J (J series)."""
+    P, w = ck["P"], ck["nbits"]
+    L = (P + 63) // 64
+    total = sum(int(it["S"], 16) for it in ck["items"]) % 2 ** (64 * L)
+    S = total >> (64 * L - P)
+    N = sum(it["N"] for it in ck["items"])
+    J = len({it["j"] for it in ck["items"]})
+    return S, N, boundary_certifies(S, P, w, N + 2 * J)
+
+
+def test_combination_on_a_small_record_filled_by_the_oracle(tmp_path):
+    # the same completion path on a record whose pieces the oracle computed,
+    # stored the way the GPU runner stores them (left-aligned limbs, hashed)
+    import oracle
+    from paper_1008_3171_amd import checkpoint
+    for f, n, w, P, pieces in ((1, 10 ** 6 + 1, 256, 320, 3), (0, 54321, 64, 100, 4)):
+        ck = checkpoint.plan(f, n, w, P, pieces)
+        L = (P + 63) // 64
+        for it in ck["items"]:
+            S, N = oracle.sum_slice(f, it["j"], n - 1, it["k0"], it["k1"], P)
+            it["S"], it["N"], it["seconds"] = "%x" % (S << (64 * L - P)), N, 0.0
+            it["hash"] = checkpoint._digest(it)
+        path = str(tmp_path / "ck.json")
+        checkpoint.save(ck, path)
+        back = checkpoint.load(path)
+        assert not checkpoint.pending(back)
+        S, N, cert = combine_on_cpu(back)
+        assert (S, N, cert) == oracle.extract(f, n, w, P)
+
+
 def test_complete_record_gives_table_2_1(record):
     raw, ck = record
     pending = [it for it in ck["items"] if it["S"] is None]
     if pending:
         pytest.skip("%d of %d pieces still to run" % (len(pending), len(ck["items"])))
     P, w = ck["P"], ck["nbits"]
-    L = (P + 63) // 64
-    total = sum(int(it["S"], 16) for it in ck["items"]) % 2 ** (64 * L)
-    S = total >> (64 * L - P)
-    N = sum(it["N"] for it in ck["items"])
-    assert boundary_certifies(S, P, w, N + 2 * 7)
+    S, N, cert = combine_on_cpu(ck)
+    assert cert
     (n, nbits, h), = read_golden("table_2_1.txt")
     assert int(n) == ck["n"] and S >> (P - w) == hex_bits(h, int(nbits))
     assert (S >> (P - 4)) & 1 == 0          # bit 2*10^15, the title's bit
