@@ -11,6 +11,16 @@ import json
 import sys
 
 
+def overlap(a: int, b: int, nbits: int, shift: int):
+    """a: the nbits bits from position n; b: the nbits bits from n - shift.
+    Returns (bits, count, agree): bits n .. n - shift + nbits - 1 as taken
+    from a, their count, and whether b holds the same bits there."""
+    count = nbits - shift
+    a_head = a >> shift                              # bits n .. n + count - 1
+    b_tail = b & ((1 << count) - 1)                  # the same positions from the second run
+    return a_head, count, a_head == b_tail
+
+
 def double_run(formula: int, n: int, nbits: int, P: int | None = None, shift: int = 4):
     """Returns (bits, count, agree): the overlap bits [n, n - shift + nbits) as
     an integer of `count` bits, and whether the two runs agree on them. Both
@@ -27,10 +37,7 @@ def double_run(formula: int, n: int, nbits: int, P: int | None = None, shift: in
         raise ValueError("a run is not certified; use a larger P")
     a = pb.to_int(a_out, P) >> (P - nbits)          # bits n .. n + nbits - 1
     b = pb.to_int(b_out, P) >> (P - nbits)          # bits n - shift .. n - shift + nbits - 1
-    count = nbits - shift
-    a_head = a >> shift                              # bits n .. n + count - 1
-    b_tail = b & ((1 << count) - 1)                  # the same positions from the second run
-    return a_head, count, a_head == b_tail
+    return overlap(a, b, nbits, shift)
 
 
 def main(argv=None):

@@ -1,5 +1,7 @@
 """Checkpoint bookkeeping (CPU): the pieces partition every series' index
-range exactly, the file round-trips, and a damaged piece is recomputed."""
+range exactly, the file round-trips, a damaged piece is recomputed, a file
+with a dropped, duplicated or overlapping piece is refused, and a corrupted
+partial that passes every file check is caught by the n / n - 4 overlap."""
 import copy
 import json
 
@@ -55,3 +57,40 @@ def test_dropped_duplicated_or_overlapping_pieces_fail_loudly(tmp_path):
         checkpoint.save(b, path)
         with pytest.raises(ValueError):
             checkpoint.load(path)
+
+
+def test_corrupted_partial_that_still_certifies_is_caught_by_the_n_minus_4_run(tmp_path):
+    # A limb flipped high in a stored partial sum, with its hash rewritten to
+    # match, passes every file check, and the guard window still certifies
+    # (the flip is far above it): only the paper's double computation, at n
+    # and n - 4, shows the bits are wrong.
+    import oracle
+    from paper_1008_3171_amd.verify import overlap
+    from test_table_2_1_record import combine_on_cpu
+    f, n, w, P = 1, 200_001, 64, 128
+    L = (P + 63) // 64
+
+    def record(pos):
+        ck = checkpoint.plan(f, pos, w, P, 2)
+        for it in ck["items"]:
+            S, N = oracle.sum_slice(f, it["j"], pos - 1, it["k0"], it["k1"], P)
+            it["S"], it["N"], it["seconds"] = "%x" % (S << (64 * L - P)), N, 0.0
+            it["hash"] = checkpoint._digest(it)
+        return ck
+
+    good, lower = record(n), record(n - 4)
+    bad = copy.deepcopy(good)
+    it = bad["items"][3]
+    it["S"] = "%x" % (int(it["S"], 16) ^ (1 << (64 * L - 20)))   # bit 20 of the result
+    it["hash"] = checkpoint._digest(it)
+    path = str(tmp_path / "bad.json")
+    checkpoint.save(bad, path)
+    bad = checkpoint.load(path)
+    assert not checkpoint.pending(bad)                  # the file checks pass
+    results = {}
+    for name, ck in (("good", good), ("bad", bad), ("lower", lower)):
+        S, N, cert = combine_on_cpu(ck)
+        assert cert, name                               # all three certify
+        results[name] = S >> (P - w)
+    assert overlap(results["good"], results["lower"], w, 4)[2]
+    assert not overlap(results["bad"], results["lower"], w, 4)[2]
