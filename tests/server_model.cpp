@@ -1,0 +1,265 @@
+// The continuous-batching server's bookkeeping on the CPU
+// (tests/test_server_model.py). server.cpp and abi.cpp run unchanged on
+// tests/fake_hip.cpp (host memory, synchronous copies) with the stand-ins
+// below for the kernels. The stand-ins check what the kernels rely on and do
+// a countable version of their work:
+//  * a head launch finds its chunk counter cleared, and its segments are
+//    numbered from chunk 0 without gaps up to the launch's chunk count;
+//  * it adds each segment's index count to its query's first counter and
+//    records the segment's index range against those counters; two launches
+//    never cover the same index of one query;
+//  * a finalize finds, for every series of its query, ranges that tile the
+//    head range [0, first tail index) exactly, and a count equal to the
+//    query's head count; it writes that count and d = n - 1 to the result row.
+// Clearing a query's counters forgets its ranges; a copy of the counters to a
+// new array (the slot pool growing) moves them.
+// The driver streams seeded queries through servers of several shapes, in
+// both pipeline modes, and checks that every query comes back once, under its
+// own tag, with its own head count.
+#include <inttypes.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <vector>
+
+#include "pibbp.h"
+#include "plan.h"
+
+extern void (*fake_hip_on_copy)(void *dst, const void *src, size_t n);
+extern size_t fake_hip_free_bytes;
+
+namespace {
+
+int g_fail = 0;
+#define CHECK(c, ...)                \
+  do {                               \
+    if (!(c)) {                      \
+      if (g_fail < 20) {             \
+        fprintf(stderr, __VA_ARGS__); \
+        fputc('\n', stderr);         \
+      }                              \
+      ++g_fail;                      \
+    }                                \
+  } while (0)
+
+using Ranges = std::map<int, std::vector<std::pair<uint64_t, uint64_t>>>;
+std::map<uintptr_t, Ranges> g_cover;  // query counters' address -> series -> index ranges
+uint64_t g_head_launches = 0, g_fin_launches = 0, g_finalized = 0;
+
+void on_copy(void *dst, const void *src, size_t n) {
+  const uintptr_t s = (uintptr_t)src, d = (uintptr_t)dst;
+  auto lo = g_cover.lower_bound(s), hi = g_cover.lower_bound(s + n);
+  std::vector<std::pair<uintptr_t, Ranges>> moved;
+  for (auto it = lo; it != hi; ++it) moved.emplace_back(it->first - s + d, std::move(it->second));
+  g_cover.erase(lo, hi);
+  for (auto &m : moved) g_cover[m.first] = std::move(m.second);
+}
+
+void head(const pibbp::HeadSeg *segs, int nseg, uint64_t nchunks, int grid,
+          unsigned long long *acc, unsigned long long *ctr) {
+  CHECK(*ctr == 0, "head launch: chunk counter not cleared");
+  *ctr = nchunks;
+  CHECK(grid >= 1 && (uint64_t)grid <= nchunks, "head launch: grid %d for %" PRIu64 " chunks",
+        grid, nchunks);
+  uint64_t c = 0;
+  for (int i = 0; i < nseg; ++i) {
+    const pibbp::HeadSeg &g = segs[i];
+    CHECK(g.chunk0 == c, "segment %d numbered from %" PRIu64 ", expected %" PRIu64, i,
+          (uint64_t)g.chunk0, c);
+    CHECK(g.ke > g.kb && g.run >= 1, "empty segment or run 0");
+    c += (g.ke - g.kb + 256ull * g.run - 1) / (256ull * g.run);
+    auto &iv = g_cover[(uintptr_t)(acc + g.acc_off)][g.j];
+    for (auto &p : iv)
+      CHECK(g.ke <= p.first || p.second <= g.kb,
+            "series %d: [%" PRIu64 ", %" PRIu64 ") launched twice", (int)g.j, (uint64_t)g.kb,
+            (uint64_t)g.ke);
+    iv.emplace_back(g.kb, g.ke);
+    acc[g.acc_off] += g.ke - g.kb;
+  }
+  CHECK(c == nchunks, "segments hold %" PRIu64 " chunks, launch says %" PRIu64, c, nchunks);
+  ++g_head_launches;
+}
+
+void finalize(const pibbp::FinQuery *qs, int nq, const unsigned long long *acc, uint64_t *out,
+              pi_status *st) {
+  for (int i = 0; i < nq; ++i) {
+    const pibbp::FinQuery &q = qs[i];
+    Ranges &r = g_cover[(uintptr_t)(acc + q.acc_off)];
+    for (int j = 0; j < 7; ++j) {
+      auto iv = r[j];
+      std::sort(iv.begin(), iv.end());
+      uint64_t at = 0;
+      for (auto &p : iv) {
+        CHECK(p.first == at, "series %d: gap or overlap at %" PRIu64, j, at);
+        at = p.second;
+      }
+      CHECK(at == q.tk0[j], "series %d: head covered to %" PRIu64 ", first tail index %" PRIu64,
+            j, at, (uint64_t)q.tk0[j]);
+    }
+    CHECK(acc[q.acc_off] == q.nhead, "head count %llu, plan %" PRIu64, acc[q.acc_off],
+          (uint64_t)q.nhead);
+    out[q.out_off] = acc[q.acc_off];
+    out[q.out_off + 1] = q.d;
+    if (q.want_status) {
+      st[q.status_idx].code = PI_OK;
+      st[q.status_idx].reserved = 0;
+      st[q.status_idx].nterms = q.nhead;
+    }
+    ++g_finalized;
+  }
+  ++g_fin_launches;
+}
+
+}  // namespace
+
+namespace pibbp {
+hipError_t launch_zero(unsigned long long *p, uint64_t n, hipStream_t) {
+  memset(p, 0, n * 8);
+  g_cover.erase(g_cover.lower_bound((uintptr_t)p), g_cover.lower_bound((uintptr_t)(p + n)));
+  return hipSuccess;
+}
+hipError_t launch_head_ptr(int, const HeadSeg *segs, int nseg, uint64_t nchunks, int grid,
+                           unsigned long long *acc, unsigned long long *ctr, hipStream_t) {
+  head(segs, nseg, nchunks, grid, acc, ctr);
+  return hipSuccess;
+}
+hipError_t launch_head_fused(const HeadSeg *segs, int nseg, uint64_t nchunks, int grid,
+                             unsigned long long *acc, unsigned long long *ctr, hipStream_t) {
+  for (int i = 0; i < nseg; ++i)
+    CHECK((segs[i].P + 63u) / 64u <= (uint32_t)kFusedMaxL, "a wide query in the fused launch");
+  head(segs, nseg, nchunks, grid, acc, ctr);
+  return hipSuccess;
+}
+hipError_t launch_head_args(int, const HeadSegTable &tab, uint64_t nchunks, int grid,
+                            unsigned long long *acc, unsigned long long *ctr, hipStream_t) {
+  head(tab.s, tab.n, nchunks, grid, acc, ctr);
+  return hipSuccess;
+}
+hipError_t launch_finalize(int, const FinQuery &single, const FinQuery *qs, int nq,
+                           const unsigned long long *acc, uint64_t *out, pi_status *status,
+                           hipStream_t) {
+  finalize(qs ? qs : &single, qs ? nq : 1, acc, out, status);
+  return hipSuccess;
+}
+hipError_t launch_finalize_fused(const FinQuery *qs, int nq, const unsigned long long *acc,
+                                 uint64_t *out, pi_status *status, hipStream_t) {
+  finalize(qs, nq, acc, out, status);
+  return hipSuccess;
+}
+hipError_t launch_combine(const uint64_t *, int, int, uint32_t, uint32_t, uint64_t, uint32_t,
+                          uint64_t *, pi_status *, hipStream_t) {
+  return hipErrorNotSupported;
+}
+int head_occupancy_fused() { return 6; }
+int head_occupancy(int Lk, bool) { return Lk <= 8 ? 7 : 4; }
+hipError_t static_scratch(unsigned long long **, uint32_t *) { return hipErrorNotSupported; }
+}  // namespace pibbp
+
+namespace {
+
+uint64_t g_state = 0x13198a2e03707344ull;
+uint64_t next_u64() {  // splitmix64
+  uint64_t z = (g_state += 0x9e3779b97f4a7c15ull);
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+uint64_t below(uint64_t n) { return n ? next_u64() % n : 0; }
+
+struct Query {
+  pi_query q;
+  bool back = false;
+};
+
+void scenario(const char *name, uint32_t max_active, uint64_t step_terms, size_t mem_limit,
+              int depth, int count, int max_bits) {
+  std::vector<Query> qs(count);
+  for (Query &x : qs) {
+    memset(&x.q, 0, sizeof x.q);
+    x.q.formula = (int32_t)below(2);
+    x.q.n = 1 + below(1ull << (1 + below(max_bits)));      // log-uniform positions
+    x.q.nbits = 1 + (uint32_t)below(256);
+    x.q.P = x.q.nbits + (uint32_t)below(PI_MAX_P - x.q.nbits + 1);
+  }
+  pi_server *s = nullptr;
+  int rc = pi_server_create(max_active, step_terms, nullptr, &s);
+  CHECK(rc == PI_OK && s, "%s: create -> %d", name, rc);
+  if (!s) return;
+  if (mem_limit) CHECK(pi_server_set_memory_limit(s, mem_limit) == PI_OK, "memory limit");
+  CHECK(pi_server_set_pipeline(s, depth) == PI_OK, "pipeline");
+  const uint32_t cap = pi_server_capacity(s);
+  size_t next = 0, back = 0;
+  uint64_t steps = 0;
+  uint32_t most = 0;
+  std::vector<pi_result> res(64);
+  while (back < qs.size()) {
+    while (next < qs.size()) {
+      rc = pi_server_submit(s, &qs[next].q, next);
+      if (rc == PI_BUSY) break;
+      CHECK(rc == PI_OK, "%s: submit %zu -> %d", name, next, rc);
+      ++next;
+    }
+    most = std::max(most, pi_server_active(s));
+    CHECK(pi_server_active(s) <= cap, "%s: %u admitted over capacity %u", name,
+          pi_server_active(s), cap);
+    uint32_t fin = 0;
+    rc = pi_server_step(s, &fin);
+    CHECK(rc == PI_OK, "%s: step -> %d", name, rc);
+    ++steps;
+    uint32_t got = 0;
+    do {
+      CHECK(pi_server_poll(s, res.data(), (uint32_t)res.size(), &got) == PI_OK, "poll");
+      for (uint32_t i = 0; i < got; ++i) {
+        const pi_result &r = res[i];
+        CHECK(r.tag < qs.size() && !qs[r.tag].back, "%s: tag %" PRIu64 " unknown or repeated",
+              name, r.tag);
+        if (r.tag >= qs.size() || qs[r.tag].back) continue;
+        Query &x = qs[r.tag];
+        x.back = true;
+        ++back;
+        const uint64_t want = pi_head_terms(x.q.formula, x.q.n);
+        // the row's second limb (d) comes back only when the query has two limbs
+        CHECK(r.code == PI_OK && r.P == x.q.P && r.limbs[0] == want && r.nterms == want &&
+                  (x.q.P <= 64 || r.limbs[1] == x.q.n - 1),
+              "%s: tag %" PRIu64 ": code %d P %u count %" PRIu64 "/%" PRIu64 " (want %" PRIu64
+              ") d %" PRIu64,
+              name, r.tag, r.code, r.P, (uint64_t)r.limbs[0], (uint64_t)r.nterms, want,
+              (uint64_t)r.limbs[1]);
+      }
+    } while (got == res.size());
+    if (steps > 2000000) {
+      CHECK(false, "%s: no progress", name);
+      break;
+    }
+  }
+  CHECK(pi_server_active(s) == 0, "%s: %u still active", name, pi_server_active(s));
+  pi_server_destroy(s);
+  printf("%s: depth %d, capacity %u, most admitted %u, %" PRIu64 " steps, %zu queries back\n", name,
+         depth, cap, most, steps, back);
+}
+
+}  // namespace
+
+int main() {
+  fake_hip_on_copy = on_copy;
+  for (int depth = 1; depth >= 0; --depth) {
+    scenario("small steps", 64, 1ull << 22, 0, depth, 200, 30);
+    scenario("pool growth", 400, 1ull << 30, 0, depth, 1200, 34);
+    scenario("memory limit", 1000, 1ull << 28, 40 * 4096, depth, 500, 32);
+    scenario("one at a time", 1, 1ull << 30, 0, depth, 40, 36);
+  }
+  // a budget below one slot admits nothing: creation fails cleanly
+  const size_t before = fake_hip_free_bytes;
+  fake_hip_free_bytes = 1 << 20;
+  pi_server *s = nullptr;
+  const int rc = pi_server_create(8, 1 << 20, nullptr, &s);
+  CHECK(rc == PI_ENOMEM && !s, "create with no memory -> %d", rc);
+  fake_hip_free_bytes = before;
+  printf("head launches %" PRIu64 ", finalize launches %" PRIu64 ", queries finalized %" PRIu64
+         ", failures %d\n",
+         g_head_launches, g_fin_launches, g_finalized, g_fail);
+  return g_fail ? 1 : 0;
+}

@@ -1,0 +1,51 @@
+"""The continuous-batching server's bookkeeping, on the CPU.
+
+tests/server_model.cpp runs server.cpp and abi.cpp unchanged on a stand-in
+HIP runtime in host memory (tests/fake_hip.cpp), with kernel stand-ins that
+count instead of compute. Seeded streams of queries (both formulas, 1 to
+1088 bits, so fused and per-limb-class launches) go through servers with
+small steps, a growing slot pool, a device-memory budget below the pool and
+one slot, in both pipeline modes. It checks that every head index of every
+query is launched exactly once, chunk tables are numbered without gaps,
+chunk counters start cleared, counters survive the pool's growth, admission
+stays within capacity, and every query comes back once, under its own tag,
+with its own head count. Built with AddressSanitizer and
+UndefinedBehaviorSanitizer.
+"""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(ROOT, "paper_1008_3171_amd", "csrc")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+
+
+@pytest.mark.skipif(shutil.which("g++") is None or
+                    not os.path.exists(os.path.join(ROCM, "include", "hip", "hip_runtime.h")),
+                    reason="needs g++ and the HIP headers")
+def test_server_bookkeeping_on_a_stand_in_runtime(tmp_path):
+    exe = str(tmp_path / "server_model")
+    cmd = ["g++", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROCM, "include"),
+           "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wall", "-Wno-unused-parameter",
+           "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=all",
+           os.path.join(HERE, "server_model.cpp"), os.path.join(HERE, "fake_hip.cpp"),
+           os.path.join(CSRC, "abi.cpp"), os.path.join(CSRC, "server.cpp"), "-pthread",
+           "-o", exe]
+    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    # verify_asan_link_order=0: the environment may preload a library of its own
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:verify_asan_link_order=0",
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    res = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=env)
+    assert res.returncode == 0, res.stderr[-4000:]
+    lines = res.stdout.splitlines()
+    assert len(lines) == 9, res.stdout
+    for l in lines[:8]:
+        name, rest = l.split(":", 1)
+        count = int(rest.rsplit(",", 1)[1].split()[0])
+        assert count in (200, 1200, 500, 40), l
+    assert lines[-1].endswith("failures 0")
