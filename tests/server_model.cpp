@@ -15,7 +15,8 @@
 // new array (the slot pool growing) moves them.
 // The driver streams seeded queries through servers of several shapes, in
 // both pipeline modes, and checks that every query comes back once, under its
-// own tag, with its own head count.
+// own tag, with its own head count; whole queries through the single-query,
+// allocation-free and batch front ends get the same checks.
 #include <inttypes.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -155,7 +156,13 @@ hipError_t launch_combine(const uint64_t *, int, int, uint32_t, uint32_t, uint64
 }
 int head_occupancy_fused() { return 6; }
 int head_occupancy(int Lk, bool) { return Lk <= 8 ? 7 : 4; }
-hipError_t static_scratch(unsigned long long **, uint32_t *) { return hipErrorNotSupported; }
+unsigned long long g_static[64];
+hipError_t static_scratch(unsigned long long **ptr, uint32_t *words) {
+  memset(g_static, 0xA5, sizeof g_static);  // holds whatever the last call left
+  *ptr = g_static;
+  *words = 64;
+  return hipSuccess;
+}
 }  // namespace pibbp
 
 namespace {
@@ -243,8 +250,64 @@ void scenario(const char *name, uint32_t max_active, uint64_t step_terms, size_t
 
 }  // namespace
 
+// Whole queries through the other front ends: one call each (pi_extract_ex,
+// pi_extract_noalloc), a batch (pi_extract_batch, and a plan launched three
+// times). Each query's row must hold its own head count (and d), and its
+// status that count.
+void front_ends(int count) {
+  std::vector<pi_query> q(count);
+  uint64_t rows = 0;
+  for (pi_query &x : q) {
+    memset(&x, 0, sizeof x);
+    x.formula = (int32_t)below(2);
+    x.n = 1 + below(1ull << (1 + below(34)));
+    x.nbits = 1 + (uint32_t)below(256);
+    x.P = x.nbits + (uint32_t)below(PI_MAX_P - x.nbits + 1);
+    x.out_offset = rows;
+    rows += (x.P + 63u) / 64u;
+  }
+  auto check = [&](const char *what, int i, const uint64_t *row, const pi_status &st) {
+    const pi_query &x = q[i];
+    const uint64_t want = pi_head_terms(x.formula, x.n);
+    CHECK(row[0] == want && (x.P <= 64 || row[1] == x.n - 1) && st.code == PI_OK &&
+              st.nterms == want,
+          "%s: query %d: count %" PRIu64 " (want %" PRIu64 "), status %d/%" PRIu64, what, i,
+          (uint64_t)row[0], want, st.code, (uint64_t)st.nterms);
+  };
+  std::vector<uint64_t> out(rows + pibbp::PI_MAX_L);
+  std::vector<pi_status> st(count);
+  for (int i = 0; i < count; ++i) {
+    uint64_t row[pibbp::PI_MAX_L] = {};
+    pi_status one = {};
+    int rc = pi_extract_ex(q[i].formula, q[i].n, q[i].nbits, q[i].P, row, &one, nullptr);
+    CHECK(rc == PI_OK, "extract_ex -> %d", rc);
+    check("extract_ex", i, row, one);
+    memset(row, 0, sizeof row);
+    memset(&one, 0, sizeof one);
+    rc = pi_extract_noalloc(q[i].formula, q[i].n, q[i].nbits, q[i].P, row, &one, nullptr);
+    CHECK(rc == PI_OK, "extract_noalloc -> %d", rc);
+    check("extract_noalloc", i, row, one);
+  }
+  int rc = pi_extract_batch(q.data(), count, out.data(), st.data(), nullptr, 0, nullptr);
+  CHECK(rc == PI_OK, "extract_batch -> %d", rc);
+  for (int i = 0; i < count; ++i) check("extract_batch", i, &out[q[i].out_offset], st[i]);
+  pi_batch *plan = nullptr;
+  rc = pi_batch_create(q.data(), count, out.data(), st.data(), &plan);
+  CHECK(rc == PI_OK && plan, "batch_create -> %d", rc);
+  for (int rep = 0; plan && rep < 3; ++rep) {
+    std::fill(out.begin(), out.end(), 0);
+    memset(st.data(), 0, st.size() * sizeof(pi_status));
+    rc = pi_batch_launch(plan, nullptr);
+    CHECK(rc == PI_OK, "batch_launch -> %d", rc);
+    for (int i = 0; i < count; ++i) check("batch plan", i, &out[q[i].out_offset], st[i]);
+  }
+  pi_batch_destroy(plan);
+  printf("front ends: %d queries\n", count);
+}
+
 int main() {
   fake_hip_on_copy = on_copy;
+  front_ends(300);
   for (int depth = 1; depth >= 0; --depth) {
     scenario("small steps", 64, 1ull << 22, 0, depth, 200, 30);
     scenario("pool growth", 400, 1ull << 30, 0, depth, 1200, 34);
