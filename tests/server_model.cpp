@@ -302,6 +302,7 @@ void front_ends(int count) {
     for (int i = 0; i < count; ++i) check("batch plan", i, &out[q[i].out_offset], st[i]);
   }
   pi_batch_destroy(plan);
+  pi_shutdown();  // the per-stream scratch and staging the library keeps
   printf("front ends: %d queries\n", count);
 }
 
