@@ -299,6 +299,18 @@ PI_API int pi_server_set_pipeline(pi_server *s, int depth);
  * an argument error. */
 PI_API int pi_server_submit(pi_server *s, const pi_query *q, uint64_t tag);
 
+/* Withdraw an admitted query that is still being summed (section 4 stops
+ * and resumes work at the granularity of jobs): it takes no part in the
+ * steps that follow, its slot is freed at once and no result is delivered
+ * for it. Chunks of it that a step already queued still run, into the freed
+ * slot, and the slot's next user clears it with a kernel queued behind them.
+ * Submitting the same query again starts it afresh. Host work only; nothing
+ * waits. With several active queries under one tag, the earliest submitted
+ * is withdrawn. PI_EINVAL when none is active under the tag: its last chunks
+ * already ran (its result is on the way), it was delivered, or the tag is
+ * unknown. */
+PI_API int pi_server_cancel(pi_server *s, uint64_t tag);
+
 /* Plan and enqueue one step on the server's stream, then wait for the
  * previous step (pipelined, the default: the host plans the next step while
  * the device runs this one) or for this one (depth 0), and deliver the

@@ -375,6 +375,8 @@ class Server:
         lib.pi_server_set_memory_limit.restype = ctypes.c_int
         lib.pi_server_set_pipeline.argtypes = [vp, ctypes.c_int]
         lib.pi_server_set_pipeline.restype = ctypes.c_int
+        lib.pi_server_cancel.argtypes = [vp, ctypes.c_uint64]
+        lib.pi_server_cancel.restype = ctypes.c_int
         for f in (lib.pi_server_create, lib.pi_server_submit, lib.pi_server_step,
                   lib.pi_server_poll):
             f.restype = ctypes.c_int
@@ -411,6 +413,16 @@ class Server:
             return False
         if rc != 0:
             raise PiError(rc, "pi_server_submit")
+        return True
+
+    def cancel(self, tag: int) -> bool:
+        """pi_server_cancel: withdraw an active query; False when none is
+        active under the tag (finishing, delivered or unknown)."""
+        rc = self._lib.pi_server_cancel(self._h, tag)
+        if rc == PI_EINVAL:
+            return False
+        if rc != 0:
+            raise PiError(rc, "pi_server_cancel")
         return True
 
     def step(self) -> int:

@@ -23,6 +23,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <deque>
 #include <map>
 #include <vector>
@@ -277,6 +278,19 @@ int pi_server_submit(pi_server *s, const pi_query *q, uint64_t tag) {
   a.nchunks = number_chunks(a.segs, cap, 0);
   s->active.push_back(std::move(a));
   return PI_OK;
+}
+
+int pi_server_cancel(pi_server *s, uint64_t tag) {
+  if (!s) return PI_EINVAL;
+  for (size_t i = 0; i < s->active.size(); ++i)
+    if (s->active[i].tag == tag) {
+      // chunks of it queued in a step still add into this slot; its next
+      // user's clearing kernel is queued behind them on the same stream
+      s->free_slots.push_back(s->active[i].slot);
+      s->active.erase(s->active.begin() + (std::ptrdiff_t)i);
+      return PI_OK;
+    }
+  return PI_EINVAL;
 }
 
 int pi_server_step(pi_server *s, uint32_t *finished) {

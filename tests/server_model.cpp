@@ -179,10 +179,14 @@ uint64_t below(uint64_t n) { return n ? next_u64() % n : 0; }
 struct Query {
   pi_query q;
   bool back = false;
+  bool cancelled = false;
 };
 
+// cancel_one_in: after a step, with probability 1/cancel_one_in, withdraw a
+// random first-submission query still out and submit it again under a new
+// tag (at most count / 5 times, so that the stream ends).
 void scenario(const char *name, uint32_t max_active, uint64_t step_terms, size_t mem_limit,
-              int depth, int count, int max_bits) {
+              int depth, int count, int max_bits, int cancel_one_in = 0) {
   std::vector<Query> qs(count);
   for (Query &x : qs) {
     memset(&x.q, 0, sizeof x.q);
@@ -198,11 +202,11 @@ void scenario(const char *name, uint32_t max_active, uint64_t step_terms, size_t
   if (mem_limit) CHECK(pi_server_set_memory_limit(s, mem_limit) == PI_OK, "memory limit");
   CHECK(pi_server_set_pipeline(s, depth) == PI_OK, "pipeline");
   const uint32_t cap = pi_server_capacity(s);
-  size_t next = 0, back = 0;
+  size_t next = 0, back = 0, cancelled = 0, refused = 0;
   uint64_t steps = 0;
   uint32_t most = 0;
   std::vector<pi_result> res(64);
-  while (back < qs.size()) {
+  while (back + cancelled < qs.size()) {
     while (next < qs.size()) {
       rc = pi_server_submit(s, &qs[next].q, next);
       if (rc == PI_BUSY) break;
@@ -221,9 +225,9 @@ void scenario(const char *name, uint32_t max_active, uint64_t step_terms, size_t
       CHECK(pi_server_poll(s, res.data(), (uint32_t)res.size(), &got) == PI_OK, "poll");
       for (uint32_t i = 0; i < got; ++i) {
         const pi_result &r = res[i];
-        CHECK(r.tag < qs.size() && !qs[r.tag].back, "%s: tag %" PRIu64 " unknown or repeated",
-              name, r.tag);
-        if (r.tag >= qs.size() || qs[r.tag].back) continue;
+        CHECK(r.tag < qs.size() && !qs[r.tag].back && !qs[r.tag].cancelled,
+              "%s: tag %" PRIu64 " unknown, repeated or withdrawn", name, r.tag);
+        if (r.tag >= qs.size() || qs[r.tag].back || qs[r.tag].cancelled) continue;
         Query &x = qs[r.tag];
         x.back = true;
         ++back;
@@ -237,6 +241,26 @@ void scenario(const char *name, uint32_t max_active, uint64_t step_terms, size_t
               (uint64_t)r.limbs[1]);
       }
     } while (got == res.size());
+    if (cancel_one_in && below(cancel_one_in) == 0 && cancelled < (size_t)count / 5) {
+      std::vector<size_t> out;
+      for (size_t t = 0; t < std::min(next, (size_t)count); ++t)
+        if (!qs[t].back && !qs[t].cancelled) out.push_back(t);
+      if (!out.empty()) {
+        const size_t t = out[below(out.size())];
+        rc = pi_server_cancel(s, t);
+        CHECK(rc == PI_OK || rc == PI_EINVAL, "%s: cancel -> %d", name, rc);
+        if (rc == PI_OK) {  // withdrawn: submit the same query again later
+          qs[t].cancelled = true;
+          ++cancelled;
+          Query again;
+          again.q = qs[t].q;
+          qs.push_back(again);
+        } else {
+          ++refused;  // its last chunks already ran: its result is on the way
+        }
+      }
+      CHECK(pi_server_cancel(s, 1ull << 40) == PI_EINVAL, "%s: unknown tag cancelled", name);
+    }
     if (steps > 2000000) {
       CHECK(false, "%s: no progress", name);
       break;
@@ -244,8 +268,10 @@ void scenario(const char *name, uint32_t max_active, uint64_t step_terms, size_t
   }
   CHECK(pi_server_active(s) == 0, "%s: %u still active", name, pi_server_active(s));
   pi_server_destroy(s);
-  printf("%s: depth %d, capacity %u, most admitted %u, %" PRIu64 " steps, %zu queries back\n", name,
-         depth, cap, most, steps, back);
+  if (cancel_one_in) CHECK(cancelled > 0, "%s: nothing was withdrawn", name);
+  printf("%s: depth %d, capacity %u, most admitted %u, %" PRIu64 " steps, %zu queries back, %zu "
+         "withdrawn and submitted again, %zu cancels refused\n",
+         name, depth, cap, most, steps, back, cancelled, refused);
 }
 
 }  // namespace
@@ -314,6 +340,7 @@ int main() {
     scenario("pool growth", 400, 1ull << 30, 0, depth, 1200, 34);
     scenario("memory limit", 1000, 1ull << 28, 40 * 4096, depth, 500, 32);
     scenario("one at a time", 1, 1ull << 30, 0, depth, 40, 36);
+    scenario("cancel and resubmit", 64, 1ull << 26, 0, depth, 300, 32, 3);
   }
   // a budget below one slot admits nothing: creation fails cleanly
   const size_t before = fake_hip_free_bytes;

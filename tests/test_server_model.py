@@ -9,12 +9,15 @@ one slot, in both pipeline modes. It checks that every head index of every
 query is launched exactly once, chunk tables are numbered without gaps,
 chunk counters start cleared, counters survive the pool's growth, admission
 stays within capacity, and every query comes back once, under its own tag,
-with its own head count. The other front ends get the same checks on 300
+with its own head count. Queries withdrawn mid-stream (pi_server_cancel)
+never come back, and the same queries submitted again come back right. The
+other front ends get the same checks on 300
 whole queries: pi_extract_ex, pi_extract_noalloc, pi_extract_batch and a
 batch plan launched three times. Built with AddressSanitizer and
 UndefinedBehaviorSanitizer.
 """
 import os
+import re
 import shutil
 import subprocess
 
@@ -45,10 +48,13 @@ def test_server_bookkeeping_on_a_stand_in_runtime(tmp_path):
     res = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=env)
     assert res.returncode == 0, res.stderr[-4000:]
     lines = res.stdout.splitlines()
-    assert len(lines) == 10, res.stdout
+    assert len(lines) == 12, res.stdout
     assert lines[0] == "front ends: 300 queries"
-    for l in lines[1:9]:
-        name, rest = l.split(":", 1)
-        count = int(rest.rsplit(",", 1)[1].split()[0])
-        assert count in (200, 1200, 500, 40), l
+    want = {"small steps": 200, "pool growth": 1200, "memory limit": 500, "one at a time": 40,
+            "cancel and resubmit": 300}
+    for l in lines[1:11]:
+        name = l.split(":", 1)[0]
+        m = re.search(r"(\d+) queries back, (\d+) withdrawn", l)
+        assert m and int(m.group(1)) == want[name], l
+        assert (int(m.group(2)) > 0) == (name == "cancel and resubmit"), l
     assert lines[-1].endswith("failures 0")
