@@ -1,7 +1,7 @@
 // The continuous-batching server's bookkeeping on the CPU
 // (tests/test_server_model.py). server.cpp and abi.cpp run unchanged on
-// tests/fake_hip.cpp (host memory, synchronous copies) with the stand-ins
-// below for the kernels. The stand-ins check what the kernels rely on and do
+// tests/fake_hip.cpp (host memory; stream work deferred until the host waits,
+// as on a device) with the stand-ins below for the kernels. The stand-ins check what the kernels rely on and do
 // a countable version of their work:
 //  * a head launch finds its chunk counter cleared, and its segments are
 //    numbered from chunk 0 without gaps up to the launch's chunk count;
@@ -23,7 +23,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <map>
+#include <memory>
 #include <vector>
 
 #include "pibbp.h"
@@ -31,6 +33,7 @@
 
 extern void (*fake_hip_on_copy)(void *dst, const void *src, size_t n);
 extern size_t fake_hip_free_bytes;
+void fake_hip_enqueue(std::function<void()> f);
 
 namespace {
 
@@ -71,7 +74,7 @@ void head(const pibbp::HeadSeg *segs, int nseg, uint64_t nchunks, int grid,
     CHECK(g.chunk0 == c, "segment %d numbered from %" PRIu64 ", expected %" PRIu64, i,
           (uint64_t)g.chunk0, c);
     CHECK(g.ke > g.kb && g.run >= 1, "empty segment or run 0");
-    c += (g.ke - g.kb + 256ull * g.run - 1) / (256ull * g.run);
+    if (g.run >= 1) c += (g.ke - g.kb + 256ull * g.run - 1) / (256ull * g.run);
     auto &iv = g_cover[(uintptr_t)(acc + g.acc_off)][g.j];
     for (auto &p : iv)
       CHECK(g.ke <= p.first || p.second <= g.kb,
@@ -117,37 +120,46 @@ void finalize(const pibbp::FinQuery *qs, int nq, const unsigned long long *acc, 
 }  // namespace
 
 namespace pibbp {
+// Each stand-in runs when the stream reaches it (fake_hip_enqueue), reading
+// device memory then; arguments passed by value are copied now, as a kernel
+// launch copies its arguments.
 hipError_t launch_zero(unsigned long long *p, uint64_t n, hipStream_t) {
-  memset(p, 0, n * 8);
-  g_cover.erase(g_cover.lower_bound((uintptr_t)p), g_cover.lower_bound((uintptr_t)(p + n)));
+  fake_hip_enqueue([=] {
+    memset(p, 0, n * 8);
+    g_cover.erase(g_cover.lower_bound((uintptr_t)p), g_cover.lower_bound((uintptr_t)(p + n)));
+  });
   return hipSuccess;
 }
 hipError_t launch_head_ptr(int, const HeadSeg *segs, int nseg, uint64_t nchunks, int grid,
                            unsigned long long *acc, unsigned long long *ctr, hipStream_t) {
-  head(segs, nseg, nchunks, grid, acc, ctr);
+  fake_hip_enqueue([=] { head(segs, nseg, nchunks, grid, acc, ctr); });
   return hipSuccess;
 }
 hipError_t launch_head_fused(const HeadSeg *segs, int nseg, uint64_t nchunks, int grid,
                              unsigned long long *acc, unsigned long long *ctr, hipStream_t) {
-  for (int i = 0; i < nseg; ++i)
-    CHECK((segs[i].P + 63u) / 64u <= (uint32_t)kFusedMaxL, "a wide query in the fused launch");
-  head(segs, nseg, nchunks, grid, acc, ctr);
+  fake_hip_enqueue([=] {
+    for (int i = 0; i < nseg; ++i)
+      CHECK((segs[i].P + 63u) / 64u <= (uint32_t)kFusedMaxL, "a wide query in the fused launch");
+    head(segs, nseg, nchunks, grid, acc, ctr);
+  });
   return hipSuccess;
 }
 hipError_t launch_head_args(int, const HeadSegTable &tab, uint64_t nchunks, int grid,
                             unsigned long long *acc, unsigned long long *ctr, hipStream_t) {
-  head(tab.s, tab.n, nchunks, grid, acc, ctr);
+  auto t = std::make_shared<HeadSegTable>(tab);
+  fake_hip_enqueue([=] { head(t->s, t->n, nchunks, grid, acc, ctr); });
   return hipSuccess;
 }
 hipError_t launch_finalize(int, const FinQuery &single, const FinQuery *qs, int nq,
                            const unsigned long long *acc, uint64_t *out, pi_status *status,
                            hipStream_t) {
-  finalize(qs ? qs : &single, qs ? nq : 1, acc, out, status);
+  const FinQuery one = single;
+  fake_hip_enqueue([=] { finalize(qs ? qs : &one, qs ? nq : 1, acc, out, status); });
   return hipSuccess;
 }
 hipError_t launch_finalize_fused(const FinQuery *qs, int nq, const unsigned long long *acc,
                                  uint64_t *out, pi_status *status, hipStream_t) {
-  finalize(qs, nq, acc, out, status);
+  fake_hip_enqueue([=] { finalize(qs, nq, acc, out, status); });
   return hipSuccess;
 }
 hipError_t launch_combine(const uint64_t *, int, int, uint32_t, uint32_t, uint64_t, uint32_t,
@@ -307,15 +319,18 @@ void front_ends(int count) {
     pi_status one = {};
     int rc = pi_extract_ex(q[i].formula, q[i].n, q[i].nbits, q[i].P, row, &one, nullptr);
     CHECK(rc == PI_OK, "extract_ex -> %d", rc);
+    (void)hipStreamSynchronize(nullptr);  // results are ready when the stream is
     check("extract_ex", i, row, one);
     memset(row, 0, sizeof row);
     memset(&one, 0, sizeof one);
     rc = pi_extract_noalloc(q[i].formula, q[i].n, q[i].nbits, q[i].P, row, &one, nullptr);
     CHECK(rc == PI_OK, "extract_noalloc -> %d", rc);
+    (void)hipStreamSynchronize(nullptr);
     check("extract_noalloc", i, row, one);
   }
   int rc = pi_extract_batch(q.data(), count, out.data(), st.data(), nullptr, 0, nullptr);
   CHECK(rc == PI_OK, "extract_batch -> %d", rc);
+  (void)hipStreamSynchronize(nullptr);
   for (int i = 0; i < count; ++i) check("extract_batch", i, &out[q[i].out_offset], st[i]);
   pi_batch *plan = nullptr;
   rc = pi_batch_create(q.data(), count, out.data(), st.data(), &plan);
@@ -325,6 +340,7 @@ void front_ends(int count) {
     memset(st.data(), 0, st.size() * sizeof(pi_status));
     rc = pi_batch_launch(plan, nullptr);
     CHECK(rc == PI_OK, "batch_launch -> %d", rc);
+    (void)hipStreamSynchronize(nullptr);
     for (int i = 0; i < count; ++i) check("batch plan", i, &out[q[i].out_offset], st[i]);
   }
   pi_batch_destroy(plan);

@@ -2,7 +2,9 @@
 
 tests/server_model.cpp runs server.cpp and abi.cpp unchanged on a stand-in
 HIP runtime in host memory (tests/fake_hip.cpp), with kernel stand-ins that
-count instead of compute. Seeded streams of queries (both formulas, 1 to
+count instead of compute. Stream work (copies and kernels) is deferred until
+the host waits for it, as on a device, so a buffer rewritten by the host
+before queued work has read it, or a result read before its wait, shows up. Seeded streams of queries (both formulas, 1 to
 1088 bits, so fused and per-limb-class launches) go through servers with
 small steps, a growing slot pool, a device-memory budget below the pool and
 one slot, in both pipeline modes. It checks that every head index of every
