@@ -196,7 +196,9 @@ struct Query {
 
 // cancel_one_in: after a step, with probability 1/cancel_one_in, withdraw a
 // random first-submission query still out and submit it again under a new
-// tag (at most count / 5 times, so that the stream ends).
+// tag (at most count / 5 times, so that the stream ends). mem_limit 1 means a
+// budget of exactly max_active slots, so that a slot a withdrawal failed to
+// free would stall the stream.
 void scenario(const char *name, uint32_t max_active, uint64_t step_terms, size_t mem_limit,
               int depth, int count, int max_bits, int cancel_one_in = 0) {
   std::vector<Query> qs(count);
@@ -211,6 +213,14 @@ void scenario(const char *name, uint32_t max_active, uint64_t step_terms, size_t
   int rc = pi_server_create(max_active, step_terms, nullptr, &s);
   CHECK(rc == PI_OK && s, "%s: create -> %d", name, rc);
   if (!s) return;
+  if (mem_limit == 1) {  // the bytes of one slot, from the capacity a large budget buys
+    pi_server *probe = nullptr;
+    CHECK(pi_server_create(1u << 30, step_terms, nullptr, &probe) == PI_OK, "probe");
+    CHECK(pi_server_set_memory_limit(probe, (size_t)1 << 32) == PI_OK, "probe limit");
+    const size_t slot = ((size_t)1 << 32) / pi_server_capacity(probe);
+    pi_server_destroy(probe);
+    mem_limit = max_active * slot + slot / 2;
+  }
   if (mem_limit) CHECK(pi_server_set_memory_limit(s, mem_limit) == PI_OK, "memory limit");
   CHECK(pi_server_set_pipeline(s, depth) == PI_OK, "pipeline");
   const uint32_t cap = pi_server_capacity(s);
@@ -273,12 +283,31 @@ void scenario(const char *name, uint32_t max_active, uint64_t step_terms, size_t
       }
       CHECK(pi_server_cancel(s, 1ull << 40) == PI_EINVAL, "%s: unknown tag cancelled", name);
     }
-    if (steps > 2000000) {
+    if (steps > 200000) {
       CHECK(false, "%s: no progress", name);
       break;
     }
   }
   CHECK(pi_server_active(s) == 0, "%s: %u still active", name, pi_server_active(s));
+  // every slot came back: a full burst is admitted at once, and finishes
+  pi_query small;
+  memset(&small, 0, sizeof small);
+  small.formula = PI_BELLARD;
+  small.n = 1000;
+  small.nbits = 32;
+  small.P = 96;
+  for (uint32_t i = 0; i < cap; ++i) {
+    rc = pi_server_submit(s, &small, 1ull << 41);
+    CHECK(rc == PI_OK, "%s: slot %u of %u not free after the stream (%d)", name, i, cap, rc);
+    if (rc != PI_OK) break;
+  }
+  for (int i = 0; i < 1000 && pi_server_active(s); ++i) {
+    uint32_t got = 0;
+    CHECK(pi_server_step(s, nullptr) == PI_OK, "step");
+    do CHECK(pi_server_poll(s, res.data(), (uint32_t)res.size(), &got) == PI_OK, "poll");
+    while (got == res.size());
+  }
+  CHECK(pi_server_active(s) == 0, "%s: the burst did not finish", name);
   pi_server_destroy(s);
   if (cancel_one_in) CHECK(cancelled > 0, "%s: nothing was withdrawn", name);
   printf("%s: depth %d, capacity %u, most admitted %u, %" PRIu64 " steps, %zu queries back, %zu "
@@ -356,7 +385,7 @@ int main() {
     scenario("pool growth", 400, 1ull << 30, 0, depth, 1200, 34);
     scenario("memory limit", 1000, 1ull << 28, 40 * 4096, depth, 500, 32);
     scenario("one at a time", 1, 1ull << 30, 0, depth, 40, 36);
-    scenario("cancel and resubmit", 64, 1ull << 26, 0, depth, 300, 32, 3);
+    scenario("cancel and resubmit", 64, 1ull << 26, 1, depth, 300, 32, 3);
   }
   // a budget below one slot admits nothing: creation fails cleanly
   const size_t before = fake_hip_free_bytes;
