@@ -18,6 +18,7 @@
 #include <map>
 
 void (*fake_hip_on_copy)(void *dst, const void *src, size_t n) = nullptr;
+void (*fake_hip_on_free)(void *p, size_t n) = nullptr;
 size_t fake_hip_total_bytes = 288ull << 30;
 size_t fake_hip_free_bytes = 280ull << 30;
 int fake_hip_cus = 256;
@@ -85,6 +86,7 @@ hipError_t hipFree(void *ptr) {
   auto it = g_dev.find(ptr);
   if (it == g_dev.end()) return hipErrorInvalidValue;
   fake_hip_free_bytes += it->second;
+  if (fake_hip_on_free) fake_hip_on_free(ptr, it->second);
   g_dev.erase(it);
   free(ptr);
   return hipSuccess;

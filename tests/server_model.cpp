@@ -32,6 +32,7 @@
 #include "plan.h"
 
 extern void (*fake_hip_on_copy)(void *dst, const void *src, size_t n);
+extern void (*fake_hip_on_free)(void *p, size_t n);
 extern size_t fake_hip_free_bytes;
 void fake_hip_enqueue(std::function<void()> f);
 
@@ -53,14 +54,22 @@ using Ranges = std::map<int, std::vector<std::pair<uint64_t, uint64_t>>>;
 std::map<uintptr_t, Ranges> g_cover;  // query counters' address -> series -> index ranges
 uint64_t g_head_launches = 0, g_fin_launches = 0, g_finalized = 0;
 
+void forget(uintptr_t p, size_t n) {
+  g_cover.erase(g_cover.lower_bound(p), g_cover.lower_bound(p + n));
+}
+
+// A copy replaces whatever the destination held; freed memory holds nothing.
 void on_copy(void *dst, const void *src, size_t n) {
   const uintptr_t s = (uintptr_t)src, d = (uintptr_t)dst;
   auto lo = g_cover.lower_bound(s), hi = g_cover.lower_bound(s + n);
   std::vector<std::pair<uintptr_t, Ranges>> moved;
   for (auto it = lo; it != hi; ++it) moved.emplace_back(it->first - s + d, std::move(it->second));
   g_cover.erase(lo, hi);
+  forget(d, n);
   for (auto &m : moved) g_cover[m.first] = std::move(m.second);
 }
+
+void on_free(void *p, size_t n) { forget((uintptr_t)p, n); }
 
 void head(const pibbp::HeadSeg *segs, int nseg, uint64_t nchunks, int grid,
           unsigned long long *acc, unsigned long long *ctr) {
@@ -106,7 +115,7 @@ void finalize(const pibbp::FinQuery *qs, int nq, const unsigned long long *acc, 
     CHECK(acc[q.acc_off] == q.nhead, "head count %llu, plan %" PRIu64, acc[q.acc_off],
           (uint64_t)q.nhead);
     out[q.out_off] = acc[q.acc_off];
-    out[q.out_off + 1] = q.d;
+    if (q.Lq >= 2) out[q.out_off + 1] = q.d;  // a batch packs rows of Lq limbs
     if (q.want_status) {
       st[q.status_idx].code = PI_OK;
       st[q.status_idx].reserved = 0;
@@ -361,6 +370,25 @@ void front_ends(int count) {
   CHECK(rc == PI_OK, "extract_batch -> %d", rc);
   (void)hipStreamSynchronize(nullptr);
   for (int i = 0; i < count; ++i) check("extract_batch", i, &out[q[i].out_offset], st[i]);
+  // two batches back to back, nothing waited for in between: the second
+  // must not rewrite the staging the first one's table upload still reads
+  {
+    const int half = count / 2;
+    std::vector<uint64_t> out2(rows + pibbp::PI_MAX_L);
+    std::vector<pi_status> st2(count);
+    std::vector<pi_query> second(q.begin() + half, q.end());
+    std::fill(out.begin(), out.end(), 0);
+    memset(st.data(), 0, st.size() * sizeof(pi_status));
+    rc = pi_extract_batch(q.data(), half, out.data(), st.data(), nullptr, 0, nullptr);
+    CHECK(rc == PI_OK, "first batch -> %d", rc);
+    rc = pi_extract_batch(second.data(), count - half, out2.data(), st2.data(), nullptr, 0,
+                          nullptr);
+    CHECK(rc == PI_OK, "second batch -> %d", rc);
+    (void)hipStreamSynchronize(nullptr);
+    for (int i = 0; i < half; ++i) check("first batch", i, &out[q[i].out_offset], st[i]);
+    for (int i = half; i < count; ++i)
+      check("second batch", i, &out2[q[i].out_offset], st2[i - half]);
+  }
   pi_batch *plan = nullptr;
   rc = pi_batch_create(q.data(), count, out.data(), st.data(), &plan);
   CHECK(rc == PI_OK && plan, "batch_create -> %d", rc);
@@ -379,6 +407,7 @@ void front_ends(int count) {
 
 int main() {
   fake_hip_on_copy = on_copy;
+  fake_hip_on_free = on_free;
   front_ends(300);
   for (int depth = 1; depth >= 0; --depth) {
     scenario("small steps", 64, 1ull << 22, 0, depth, 200, 30);

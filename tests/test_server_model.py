@@ -14,8 +14,8 @@ stays within capacity, and every query comes back once, under its own tag,
 with its own head count. Queries withdrawn mid-stream (pi_server_cancel)
 never come back, and the same queries submitted again come back right. The
 other front ends get the same checks on 300
-whole queries: pi_extract_ex, pi_extract_noalloc, pi_extract_batch and a
-batch plan launched three times. Built with AddressSanitizer and
+whole queries: pi_extract_ex, pi_extract_noalloc, pi_extract_batch (also two
+batches issued back to back) and a batch plan launched three times. Built with AddressSanitizer and
 UndefinedBehaviorSanitizer.
 """
 import os
