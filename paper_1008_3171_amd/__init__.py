@@ -375,8 +375,6 @@ class Server:
         lib.pi_server_set_memory_limit.restype = ctypes.c_int
         lib.pi_server_set_pipeline.argtypes = [vp, ctypes.c_int]
         lib.pi_server_set_pipeline.restype = ctypes.c_int
-        lib.pi_server_cancel.argtypes = [vp, ctypes.c_uint64]
-        lib.pi_server_cancel.restype = ctypes.c_int
         for f in (lib.pi_server_create, lib.pi_server_submit, lib.pi_server_step,
                   lib.pi_server_poll):
             f.restype = ctypes.c_int
@@ -418,7 +416,10 @@ class Server:
     def cancel(self, tag: int) -> bool:
         """pi_server_cancel: withdraw an active query; False when none is
         active under the tag (finishing, delivered or unknown)."""
-        rc = self._lib.pi_server_cancel(self._h, tag)
+        f = self._lib.pi_server_cancel
+        f.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+        f.restype = ctypes.c_int
+        rc = f(self._h, tag)
         if rc == PI_EINVAL:
             return False
         if rc != 0:
