@@ -299,8 +299,9 @@ PI_API int pi_server_set_pipeline(pi_server *s, int depth);
  * an argument error. */
 PI_API int pi_server_submit(pi_server *s, const pi_query *q, uint64_t tag);
 
-/* Withdraw an admitted query that is still being summed (section 4 stops
- * and resumes work at the granularity of jobs): it takes no part in the
+/* Withdraw an admitted query that is still being summed (section 4 lets
+ * running jobs be killed and the computation be resumed later; here one
+ * query is dropped and may be submitted again): it takes no part in the
  * steps that follow, its slot is freed at once and no result is delivered
  * for it. Chunks of it that a step already queued still run, into the freed
  * slot, and the slot's next user clears it with a kernel queued behind them.
