@@ -405,6 +405,71 @@ void front_ends(int count) {
   printf("front ends: %d queries\n", count);
 }
 
+// The memory budget cut below what is admitted, mid-stream: nothing more is
+// admitted until the active queries fit it, and every result still comes back.
+void shrinking_budget(int depth) {
+  pi_server *s = nullptr;
+  CHECK(pi_server_create(64, 1ull << 24, nullptr, &s) == PI_OK, "create");
+  CHECK(pi_server_set_pipeline(s, depth) == PI_OK, "pipeline");
+  size_t slot = 0;  // the bytes of one slot, from the capacity a large budget buys
+  {
+    pi_server *probe = nullptr;
+    CHECK(pi_server_create(1u << 30, 1ull << 24, nullptr, &probe) == PI_OK, "probe");
+    CHECK(pi_server_set_memory_limit(probe, (size_t)1 << 32) == PI_OK, "probe limit");
+    slot = ((size_t)1 << 32) / pi_server_capacity(probe);
+    pi_server_destroy(probe);
+  }
+  std::vector<pi_query> q(120);
+  for (pi_query &x : q) {
+    memset(&x, 0, sizeof x);
+    x.formula = (int32_t)below(2);
+    x.n = 1 + below(1ull << (1 + below(30)));
+    x.nbits = 64;
+    x.P = 64 + (uint32_t)below(PI_MAX_P - 63);
+  }
+  CHECK(pi_server_set_memory_limit(s, 64 * slot + slot / 2) == PI_OK, "limit");
+  size_t next = 0, back = 0, steps = 0, refused = 0;
+  std::vector<bool> seen(q.size(), false);
+  std::vector<pi_result> res(64);
+  while (back < q.size() && steps < 200000) {
+    while (next < q.size()) {
+      const uint32_t before = pi_server_active(s);
+      const int rc = pi_server_submit(s, &q[next], next);
+      if (rc == PI_BUSY) {
+        CHECK(before >= pi_server_capacity(s) || before >= 64, "busy with room: %u of %u", before,
+              pi_server_capacity(s));
+        ++refused;
+        break;
+      }
+      CHECK(rc == PI_OK && before < pi_server_capacity(s), "admitted %u over capacity %u", before,
+            pi_server_capacity(s));
+      ++next;
+    }
+    CHECK(pi_server_step(s, nullptr) == PI_OK, "step");
+    if (++steps == 3)  // cut the budget to 10 slots while about 64 queries are in
+      CHECK(pi_server_set_memory_limit(s, 10 * slot + slot / 2) == PI_OK &&
+                pi_server_capacity(s) == 10,
+            "cut budget");
+    uint32_t got = 0;
+    do {
+      CHECK(pi_server_poll(s, res.data(), (uint32_t)res.size(), &got) == PI_OK, "poll");
+      for (uint32_t i = 0; i < got; ++i) {
+        const pi_result &r = res[i];
+        CHECK(r.tag < q.size() && !seen[r.tag], "tag %" PRIu64 " unknown or repeated", r.tag);
+        if (r.tag >= q.size() || seen[r.tag]) continue;
+        seen[r.tag] = true;
+        ++back;
+        const uint64_t want = pi_head_terms(q[r.tag].formula, q[r.tag].n);
+        CHECK(r.code == PI_OK && r.limbs[0] == want, "shrinking budget: tag %" PRIu64, r.tag);
+      }
+    } while (got == res.size());
+  }
+  CHECK(back == q.size(), "shrinking budget: %zu of %zu back", back, q.size());
+  pi_server_destroy(s);
+  printf("shrinking budget: depth %d, %zu steps, %zu queries back, %zu submissions refused\n",
+         depth, steps, back, refused);
+}
+
 int main() {
   fake_hip_on_copy = on_copy;
   fake_hip_on_free = on_free;
@@ -415,6 +480,7 @@ int main() {
     scenario("memory limit", 1000, 1ull << 28, 40 * 4096, depth, 500, 32);
     scenario("one at a time", 1, 1ull << 30, 0, depth, 40, 36);
     scenario("cancel and resubmit", 64, 1ull << 26, 1, depth, 300, 32, 3);
+    shrinking_budget(depth);
   }
   // a budget below one slot admits nothing: creation fails cleanly
   const size_t before = fake_hip_free_bytes;

@@ -12,7 +12,9 @@ query is launched exactly once, chunk tables are numbered without gaps,
 chunk counters start cleared, counters survive the pool's growth, admission
 stays within capacity, and every query comes back once, under its own tag,
 with its own head count. Queries withdrawn mid-stream (pi_server_cancel)
-never come back, and the same queries submitted again come back right. The
+never come back, and the same queries submitted again come back right. A
+memory budget cut below what is admitted stops admission until the active
+queries fit, and loses nothing. The
 other front ends get the same checks on 300
 whole queries: pi_extract_ex, pi_extract_noalloc, pi_extract_batch (also two
 batches issued back to back) and a batch plan launched three times. Built with AddressSanitizer and
@@ -63,13 +65,17 @@ def test_server_bookkeeping_on_a_stand_in_runtime(tmp_path):
     assert fast.returncode == 0, fast.stderr[-4000:]
     assert fast.stdout == res.stdout
     lines = res.stdout.splitlines()
-    assert len(lines) == 12, res.stdout
+    assert len(lines) == 14, res.stdout
     assert lines[0] == "front ends: 300 queries"
     want = {"small steps": 200, "pool growth": 1200, "memory limit": 500, "one at a time": 40,
             "cancel and resubmit": 300}
-    for l in lines[1:11]:
+    streams = [l for l in lines if "withdrawn" in l]
+    assert len(streams) == 10, res.stdout
+    for l in streams:
         name = l.split(":", 1)[0]
         m = re.search(r"(\d+) queries back, (\d+) withdrawn", l)
         assert m and int(m.group(1)) == want[name], l
         assert (int(m.group(2)) > 0) == (name == "cancel and resubmit"), l
+    shrink = [l for l in lines if l.startswith("shrinking budget")]
+    assert len(shrink) == 2 and all("120 queries back" in l for l in shrink), res.stdout
     assert lines[-1].endswith("failures 0")
