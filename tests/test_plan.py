@@ -147,3 +147,17 @@ def test_plan_errors():
                             ctypes.byref(count)) == pb.PI_EUNSUPPORTED
     # an empty range plans nothing
     assert pb.plan_head(pb.BELLARD, 10 ** 6, 96, 5, 5) == []
+
+
+def test_instruction_model_uses_the_planners_class_cuts():
+    # bench.py's per-term model splits each series at the same moduli as the
+    # planner (fast arithmetic), so it prices every segment at its own class
+    import bench
+    firsts = [m for _, m, _, _, _, _, _ in bench.KERNEL_CLASSES]
+    assert firsts == [0] + [2 ** lo for _, lo, _ in FAST[1:]]
+    names = [name for name, *_ in bench.KERNEL_CLASSES]
+    assert names == ["22", "27", "29", "f4", "f3", "f2", "fs", "62"]
+    # and the model's head-term count is the planner's
+    for f, n in ((pb.BELLARD, 10 ** 12), (pb.BBP, 10 ** 10), (pb.BELLARD, 2 * 10 ** 15)):
+        ops, terms = bench.valu_ops_per_launch(f, n, 320)
+        assert terms == pb.head_terms(f, n) and ops > 0
