@@ -1,10 +1,10 @@
-// A host-only driver for the library's planning code (abi.cpp, server.cpp)
+// A host-only test program for the library's planning code (abi.cpp, server.cpp)
 // built with AddressSanitizer and UndefinedBehaviorSanitizer
-// (tests/test_host_sanitized.py). The kernels are not part of this build:
+// (tests/test_host_sanitized.py). The kernels are not linked in:
 // every launcher below is a stand-in that reports "no device" and counts its
 // calls, and the HIP runtime finds no GPU on the build host, so each entry
 // point runs its argument checks and planning and stops at its first device
-// call. The driver prints every result as text; the test compares the
+// call. The program prints every result as text; the test compares the
 // sanitized build with a plain one.
 #include <inttypes.h>
 #include <stdint.h>

@@ -1,5 +1,5 @@
 /*
- * A driver for the oracle built with AddressSanitizer and UndefinedBehavior-
+ * A test program for the oracle built with AddressSanitizer and UndefinedBehavior-
  * Sanitizer (tests/test_oracle_sanitized.py): it calls every oracle entry
  * point at the edges of its arguments (one-bit and 1088-bit sums, the limits
  * of the word arithmetic, tail terms with modulus 1, empty and tail-only

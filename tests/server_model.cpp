@@ -13,7 +13,7 @@
 //    query's head count; it writes that count and d = n - 1 to the result row.
 // Clearing a query's counters forgets its ranges; a copy of the counters to a
 // new array (the slot pool growing) moves them.
-// The driver streams seeded queries through servers of several shapes, in
+// The program streams seeded queries through servers of several shapes, in
 // both pipeline modes, and checks that every query comes back once, under its
 // own tag, with its own head count; whole queries through the single-query,
 // allocation-free and batch front ends get the same checks.

@@ -5,7 +5,7 @@ UndefinedBehaviorSanitizer, on the CPU.
 tests/host_sanitize.cpp links abi.cpp and server.cpp, built with g++ for the
 host only, with stand-ins for the kernel launchers. On a host without a GPU
 every entry point runs its checks and planning and stops at its first device
-call. Built once with the sanitizers and once without, the driver must run
+call. Built once with the sanitizers and once without, the program must run
 clean and print the same results.
 """
 import os
@@ -39,7 +39,7 @@ def test_host_code_runs_clean_under_sanitizers_and_matches_the_plain_build(tmp_p
     plain = build(tmp_path, "plain", ["-O2"])
     san = build(tmp_path, "san", ["-O1", "-g", "-fno-omit-frame-pointer",
                                   "-fsanitize=address,undefined", "-fno-sanitize-recover=all"])
-    # no GPU for this process even where one exists: the driver expects none
+    # no GPU for this process even where one exists: the program expects none
     env = dict(os.environ, HIP_VISIBLE_DEVICES="-1", ROCR_VISIBLE_DEVICES="-1")
     want = subprocess.run([plain], capture_output=True, text=True, timeout=300, env=env)
     assert want.returncode == 0, want.stderr[-4000:]
